@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of the even-odd Wilson-Dirac hot path on one MI355X.
+
+Workload (one "step"): the 48^3x96 lattice (links exp(i 0.3 H), seed 5,
+antiperiodic in t), kappa = 0.124, the 12 spin-colour point sources at the
+origin solved together by reliable-update BiCGstab with binary16 storage +
+per-site norm (FP32 arithmetic, FP64 reductions, FP64 reliable updates and
+solution), 12-real links, delta = 0.1, to a true FP64 residual of 1e-12.
+One step runs the whole path: even-odd source preparation, the multi-RHS
+M_hat applications, the fused BLAS-1 kernels and reductions, the reliable
+updates and the reconstruction of the full-lattice solution.
+
+Reported:
+  value            algorithmic GB/s of the whole step (sum of every kernel's
+                   algorithmic bytes under the method's storage formats, divided
+                   by the step's wall time)
+  roofline         the dominant kernel (12-RHS binary16 dslash): algorithmic
+                   bytes per launch / average launch time (HIP events on its
+                   stream), against 8 TB/s
+  time_to_solution mixed 12-RHS batch vs the plain FP64 single-RHS BiCGstab
+  cpu_baseline     the FP64 oracle on a bounded sample (see --help)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (48, 48, 48, 96)
+KAPPA = 0.124
+EPS, SEED = 0.3, 5
+NRHS = 12
+
+# Algorithmic bytes per site (one parity) under the storage formats:
+# spinor 24 reals (+ a 4-byte norm for 16-bit), link 12 reals.
+SPINOR_B = {"fp64": 192, "fp32": 96, "i16": 52, "f16": 52}
+LINK_B = {"fp64": 96, "fp32": 48, "i16": 24, "f16": 24}
+
+
+def dslash_bytes(prec: str, nrhs: int, xpay: int = 0) -> int:
+    """Per output site: 8 links once per launch, nrhs input and output spinors
+    (+ xpay extra spinor reads per RHS)."""
+    return 8 * LINK_B[prec] + nrhs * SPINOR_B[prec] * (2 + xpay)
+
+
+def bicgstab_iter_bytes(prec: str, nrhs: int) -> int:
+    """One BiCGstab iteration for nrhs RHS, per site: 2 M_hat (4 dslash, the
+    second of each with the xpay read and, for v, the <r~,v> read of r~) and
+    the BLAS-1 passes (p: 3R+1W, s: 2R+1W, x/r: 5R+2W)."""
+    s = SPINOR_B[prec]
+    return (dslash_bytes(prec, nrhs) * 2 + dslash_bytes(prec, nrhs, 1) * 2 + nrhs * s  # <r~,v>
+            + nrhs * s * (4 + 3 + 7))
+
+
+def ru_bytes(prec: str, nrhs: int) -> int:
+    """One reliable update (FP64): x += x^ (R x, R x^, W x), M_hat x (2 dslash),
+    r = b - r (2R+1W), re-encode (R r, R r~, W r^, W x^, R r^)."""
+    s64, s = SPINOR_B["fp64"], SPINOR_B[prec]
+    return (nrhs * (2 * s64 + s) + dslash_bytes("fp64", nrhs) + dslash_bytes("fp64", nrhs, 1)
+            + nrhs * 3 * s64 + nrhs * (s64 + 4 * s))
+
+
+def prepare_bytes(nrhs: int) -> int:
+    """Even-odd prepare and reconstruct in FP64 (per site of one parity):
+    encode b_e, b_o (2 x 192 read + write), |b|^2, b_hat dslash, x = 0,
+    first residual (M_hat + r = b - r), reconstruct (encode b_o, dslash, decode 2)."""
+    s64 = SPINOR_B["fp64"]
+    return (nrhs * 4 * s64 + nrhs * 2 * s64 + dslash_bytes("fp64", nrhs, 1) + nrhs * s64
+            + dslash_bytes("fp64", nrhs) + dslash_bytes("fp64", nrhs, 1) + nrhs * 3 * s64
+            + nrhs * 2 * s64 + dslash_bytes("fp64", nrhs, 1) + nrhs * 4 * s64)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", default="f16", choices=["f16", "i16", "fp32"])
+    ap.add_argument("--dims", default="x".join(map(str, DIMS)))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--dslash-reps", type=int, default=20)
+    ap.add_argument("--cpu-sample-sites", type=int, default=200000,
+                    help="output sites of the oracle dslash timed for the CPU baseline")
+    ap.add_argument("--copy-probe-gb", type=float, default=0.0,
+                    help="also run a plain device copy of this many GB (counter scaling)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "part of this build (--gpus must be 1)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_0911_3191_amd as wd
+    import wdinputs
+
+    dims = tuple(int(v) for v in args.dims.split("x"))
+    V = int(np.prod(dims))
+    Vh = V // 2
+    dev = torch.device("cuda:0")
+    inner = args.inner
+
+    log(f"generating links {dims} eps={EPS} seed={SEED}")
+    t0 = time.time()
+    U = wdinputs.gauge_random(dims, EPS, SEED)
+    log(f"links generated in {time.time() - t0:.1f}s")
+    lat = wd.lattice(dims, True)
+    U_dev = torch.from_numpy(U).to(dev)
+    gauge = wd.Gauge(lat, U_dev, ("fp64", "fp32", "i16", "f16"))
+    torch.cuda.synchronize()
+    del U_dev
+    torch.cuda.empty_cache()
+
+    # 12 spin-colour point sources at the origin, built in place on the device
+    b = torch.zeros((NRHS, V, 4, 3, 2), dtype=torch.float64, device=dev)
+    for s in range(4):
+        for c in range(3):
+            b[3 * s + c, 0, s, c, 0] = 1.0
+    x = torch.zeros_like(b)
+    stream = torch.cuda.Stream()
+    params = wd.solve_params(tol=1e-12, maxiter=20000, inner=inner, delta=0.1, nrhs=NRHS, use_graph=True)
+    ws = wd.new_workspace(lat, params, "bicgstab")
+    log(f"workspace {ws.numel() / 1e9:.1f} GB; warmup {args.warmup}, steps {args.steps}")
+
+    def step():
+        with torch.cuda.stream(stream):
+            st, infos = wd.bicgstab_solve(gauge, KAPPA, x, b, params, ws, stream)
+        return st, infos
+
+    for i in range(args.warmup):
+        st, infos = step()
+        log(f"warmup {i}: status {st} iters {[inf['iters'] for inf in infos]}")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    all_infos = []
+    for i in range(args.steps):
+        st, infos = step()
+        all_infos.append(infos)
+        log(f"step {i}: status {st} iters max {max(inf['iters'] for inf in infos)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed / args.steps * 1e3
+    infos = all_infos[-1]
+    iters = [inf["iters"] for inf in infos]
+    rus = [inf["reliable_updates"] for inf in infos]
+    worst_res = max(inf["true_rel_resid"] for inf in infos)
+    loops = max(iters)  # batch iterations (k + l), the batch runs until the slowest RHS is done
+    n_it = max(i - r for i, r in zip(iters, rus))
+    n_ru = max(rus)
+    step_bytes = Vh * (n_it * bicgstab_iter_bytes(inner, NRHS) + n_ru * ru_bytes(inner, NRHS)
+                       + prepare_bytes(NRHS))
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    # ---- FP64 single-RHS reference solve (same source 0) ----
+    fp64 = None
+    if not args.no_fp64_reference:
+        p64 = wd.solve_params(tol=1e-12, maxiter=20000, inner="fp64", delta=0.0, nrhs=1, use_graph=True)
+        del ws
+        torch.cuda.empty_cache()
+        ws64 = wd.new_workspace(lat, p64, "bicgstab")
+        b0 = b[0:1].contiguous()
+        x0 = torch.zeros_like(b0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            st64, inf64 = wd.bicgstab_solve(gauge, KAPPA, x0, b0, p64, ws64, stream)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        fp64 = {"seconds": t64, "iters": inf64[0]["iters"], "true_rel_resid": inf64[0]["true_rel_resid"],
+                "status": st64}
+        log(f"fp64 reference: {t64:.3f}s iters {inf64[0]['iters']}")
+        del ws64, b0, x0
+        torch.cuda.empty_cache()
+
+    # ---- dominant kernel: 12-RHS dslash in the inner precision, HIP events on its stream ----
+    fin = wd.new_field(lat, inner, NRHS)
+    fout = wd.new_field(lat, inner, NRHS)
+    with torch.cuda.stream(stream):
+        wd.wd_spinor_encode_full(lat, inner, NRHS, 1, fin, b, stream)
+        for _ in range(3):
+            wd.wilson_dslash(gauge, fout, fin, 0, 0, inner, NRHS, stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.dslash_reps):
+            wd.wilson_dslash(gauge, fout, fin, 0, 0, inner, NRHS, stream)
+        ev1.record(stream)
+    ev1.synchronize()
+    t_dslash = ev0.elapsed_time(ev1) / args.dslash_reps * 1e-3
+    dbytes = dslash_bytes(inner, NRHS) * Vh
+    achieved = dbytes / t_dslash / 1e9
+    del fin, fout
+
+    # single-RHS dslash in every precision (context for the roofline)
+    table = {}
+    for prec in ("fp64", "fp32", "i16", "f16"):
+        fi = wd.new_field(lat, prec, 1)
+        fo = wd.new_field(lat, prec, 1)
+        with torch.cuda.stream(stream):
+            wd.wd_spinor_encode_full(lat, prec, 1, 1, fi, b[0:1], stream)
+            for _ in range(3):
+                wd.wilson_dslash(gauge, fo, fi, 0, 0, prec, 1, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.dslash_reps):
+                wd.wilson_dslash(gauge, fo, fi, 0, 0, prec, 1, stream)
+            e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / args.dslash_reps * 1e-3
+        gbs = dslash_bytes(prec, 1) * Vh / t / 1e9
+        table[prec] = {"us": round(t * 1e6, 1), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "gflops": round(1320 * Vh / t / 1e9, 1)}
+        del fi, fo
+    log(f"dslash table {table}")
+
+    if args.copy_probe_gb > 0:
+        n = int(args.copy_probe_gb * 1e9) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 8 / 1e9:.2f} GB read + written, 3 launches")
+        del src, dst
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        psi = np.zeros((Vh, 4, 3, 2))
+        psi[:, 0, 0, 0] = 1.0
+        rng = np.random.default_rng(0)
+        cbs = rng.choice(Vh, size=min(args.cpu_sample_sites, Vh), replace=False)
+        oracle.dslash_parity_sites(dims, U, psi, 0, cbs[:1000])  # load + warm
+        t2 = time.perf_counter()
+        oracle.dslash_parity_sites(dims, U, psi, 0, cbs)
+        t_site = (time.perf_counter() - t2) / len(cbs)
+        # the oracle doing the same solve: per batch iteration 4 dslash per RHS (BLAS-1 ignored)
+        t_iter = 4 * t_site * Vh * NRHS
+        cpu_value = bicgstab_iter_bytes(inner, NRHS) * Vh / t_iter / 1e9
+        cpu = {"value": round(cpu_value, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+               "sample": (f"FP64 oracle dslash at {len(cbs)} random output sites of {args.dims} "
+                          f"({t_site * 1e6:.2f} us/site); one solver iteration extrapolated as 4 "
+                          f"dslash per RHS over all {Vh} sites x {NRHS} RHS, BLAS-1 not counted; "
+                          f"value = the step's algorithmic bytes per iteration / that time")}
+        log(f"cpu baseline {cpu}")
+
+    per_rhs_mixed = ms_per_step * 1e-3 / NRHS
+    out = {
+        "metric": "dslash GB/s & % HBM roofline; time-to-1e-12 mixed vs FP64; serve p50/p99",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.dims} 12-RHS {inner}-storage RU-BiCGstab to 1e-12",
+                   "lattice": args.dims, "kappa": KAPPA, "eps": EPS, "seed": SEED, "nrhs": NRHS,
+                   "sources": "12 spin-colour point sources at the origin", "inner": inner,
+                   "delta": 0.1, "recon": 12, "graph": True, "arith": "f32 inner, f64 reductions/updates"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"dslash_kernel<{inner}> 12-RHS", "bytes_per_launch": dbytes,
+                     "us_per_launch": round(t_dslash * 1e6, 1)},
+        "time_to_solution": {"mixed_batch_s": round(ms_per_step * 1e-3, 3),
+                             "mixed_per_rhs_s": round(per_rhs_mixed, 4),
+                             "fp64_single_rhs_s": round(fp64["seconds"], 3) if fp64 else None,
+                             "speedup_per_rhs": round(fp64["seconds"] / per_rhs_mixed, 2) if fp64 else None,
+                             "iters_mixed_max": max(iters), "reliable_updates_max": n_ru,
+                             "iters_fp64": fp64["iters"] if fp64 else None,
+                             "true_rel_resid_max": worst_res,
+                             "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None},
+        "dslash_single_rhs": table,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

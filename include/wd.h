@@ -1,0 +1,235 @@
+/*
+ * wd.h -- C ABI of the MI355X Wilson-Dirac library (libwdslash.so).
+ *
+ * The library applies the even-odd preconditioned Wilson-Dirac operator and
+ * solves with it, following Clark, Babich, Barros, Brower and Rebbi, "Solving
+ * Lattice QCD systems of equations using mixed precision solvers on GPUs"
+ * (arXiv:0911.3191):
+ *   - hopping term D of the Wilson-Dirac matrix (Section 3, Eq. 1), gamma
+ *     matrices in the DeGrand-Rossi basis (Appendix B);
+ *   - Schur complement on the even sites M_hat = 1 - kappa^2 D_eo D_oe with
+ *     kappa = 1/(2(4+m)) (Section 3, Eq. 2);
+ *   - 12-real SU(3) link storage, c = (a x b)^* (Appendix A.1);
+ *   - FP64, FP32 and 16-bit storage with a per-site norm (Section 4.6);
+ *   - BiCGstab on M_hat and CG on the normal equations (Section 5.1), with
+ *     the reliable-update mixed-precision scheme (Section 5.3, Algorithm 2)
+ *     and the defect-correction scheme (Section 5.2, Algorithm 1).
+ *
+ * Conventions
+ *   Lattice dims (Lx, Ly, Lz, Lt), all even, each >= 2.  Direction mu = 0..3
+ *   is x, y, z, t (the paper's mu = 1..4).  Site index
+ *   lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2 (0 = even);
+ *   checkerboard index cb = lex / 2 within a parity.  Periodic in x, y, z;
+ *   in t periodic or antiperiodic (t_antiperiodic = 1: every hop across the t
+ *   boundary is multiplied by -1; the stored links are never changed).
+ *   The library solves (1 - kappa D) x = b, i.e. the paper's M x = b with b
+ *   divided by (4 + m).
+ *
+ * Canonical (caller-visible) layouts, FP64 on the device, complex = (re, im):
+ *   gauge        double U[V][4][3][3][2]: U[lex][mu] is the link lex -> lex+mu,
+ *                acting as (U psi)_a = sum_b U[a][b] psi_b.
+ *   full spinor  double psi[nrhs][V][4][3][2] (spin, colour), DeGrand-Rossi.
+ *   parity spinor double psi[nrhs][Vh][4][3][2], sites of one parity in cb order.
+ *
+ * Device field formats (opaque to the caller; sizes from wd_spinor_bytes):
+ *   encoded spinor fields of one parity for nrhs right-hand sides, in one of
+ *   the wd_prec storage formats.  Only the library reads or writes them.
+ *
+ * Memory and streams
+ *   The caller allocates every device buffer (for example as PyTorch tensors)
+ *   and passes raw device pointers; the library never frees caller memory and
+ *   never allocates device memory in the operator or solver paths.  `stream`
+ *   is a hipStream_t (NULL = default stream).  Device pointers must be 16-byte
+ *   aligned (256-byte alignment is recommended).
+ *
+ * Errors
+ *   Every entry point validates its arguments before launching anything and
+ *   returns a wd_status; no exception crosses the ABI.  wd_last_error() gives a
+ *   thread-local message for the last failing call on the calling thread.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wd_status;
+#define WD_OK 0
+#define WD_NOT_CONVERGED 1
+#define WD_EINVAL (-1)
+#define WD_ENOMEM (-2)
+#define WD_EDEVICE (-3)
+#define WD_EBREAKDOWN (-4)
+#define WD_EUNSUPPORTED (-5)
+
+/* Storage precision of fields (arithmetic is FP64 for WD_FP64, FP32 for the
+ * others).  The 16-bit formats keep one binary32 norm per site (the largest
+ * |real| among the site's 24 reals) and store each real relative to it:
+ * WD_HALF_I16 as int16 fixed point q = rint(v * 32767/norm) (the paper's
+ * format, Section 4.6), WD_HALF_F16 as IEEE binary16 v/norm.  16-bit links
+ * carry no norm (their reals lie in [-1, 1]). */
+typedef int32_t wd_prec;
+#define WD_FP64 0
+#define WD_FP32 1
+#define WD_HALF_I16 2
+#define WD_HALF_F16 3
+#define WD_PREC_MASK(p) (1u << (p))
+
+typedef struct {
+  int32_t dims[4];        /* Lx, Ly, Lz, Lt */
+  int32_t t_antiperiodic; /* 1: antiperiodic in t, 0: periodic */
+} wd_lattice;
+
+typedef struct wd_gauge wd_gauge;   /* resident gauge field (read-only once built) */
+typedef struct wd_solver wd_solver; /* an in-flight solve (step API) */
+
+/* Thread-local message for the last failing call ("" if none). */
+const char *wd_last_error(void);
+
+/* Library version string. */
+const char *wd_version(void);
+
+/* ---- gauge field ----------------------------------------------------------- */
+
+/* Device bytes needed to hold the gauge field in every precision of
+ * prec_mask (a bitwise OR of WD_PREC_MASK(p)), each stored as 12 reals per
+ * link (rows a and b of Appendix A.1).  0 on invalid arguments. */
+size_t wd_gauge_bytes(const wd_lattice *lat, uint32_t prec_mask);
+
+/* Build a resident gauge field from the canonical FP64 links U_dev (device,
+ * [V][4][3][3][2]).  The encoded copies are written into dev_buf (caller-owned,
+ * >= wd_gauge_bytes bytes, kept alive until wd_gauge_destroy).  The handle
+ * itself is host metadata.  Asynchronous on stream; U_dev may be released once
+ * the stream has passed this point.  Links must be SU(3) to rounding (the third
+ * row is rebuilt as (a x b)^*). */
+wd_status wd_gauge_create(const wd_lattice *lat, const double *U_dev, uint32_t prec_mask,
+                          void *dev_buf, size_t bytes, void *stream, wd_gauge **out);
+void wd_gauge_destroy(wd_gauge *g);
+
+/* ---- spinor fields ------------------------------------------------------------ */
+
+/* Device bytes of one encoded parity field with nrhs right-hand sides. */
+size_t wd_spinor_bytes(const wd_lattice *lat, wd_prec prec, int32_t nrhs);
+
+/* Encode canonical FP64 parity spinors (device, [nrhs][Vh][4][3][2]) into the
+ * device field `field` of precision prec.  16-bit formats: per-site norm and
+ * quantisation computed in binary32 from the binary32-rounded input,
+ * round-to-nearest-even (Section 4.6). */
+wd_status wd_spinor_encode(const wd_lattice *lat, wd_prec prec, int32_t nrhs, void *field,
+                           const double *canon, void *stream);
+
+/* Decode a device field into canonical FP64 parity spinors. */
+wd_status wd_spinor_decode(const wd_lattice *lat, wd_prec prec, int32_t nrhs, double *canon,
+                           const void *field, void *stream);
+
+/* Encode the parity-`parity` sites of canonical FP64 full-lattice spinors
+ * (device, [nrhs][V][4][3][2]) into a parity field (the even-odd split of
+ * Section 3). */
+wd_status wd_spinor_encode_full(const wd_lattice *lat, wd_prec prec, int32_t nrhs, int32_t parity,
+                                void *field, const double *canon_full, void *stream);
+
+/* Decode a parity field into the parity-`parity` sites of canonical FP64
+ * full-lattice spinors; the other sites of canon_full are left untouched. */
+wd_status wd_spinor_decode_full(const wd_lattice *lat, wd_prec prec, int32_t nrhs, int32_t parity,
+                                double *canon_full, const void *field, void *stream);
+
+/* ---- operators ------------------------------------------------------------------ */
+
+/* Hopping term restricted to parities (Eq. 1): out_p = D_{p,1-p} in_{1-p}, or
+ * its adjoint (dagger = 1: projectors 1 -+ gamma_mu swapped, links daggered).
+ * out and in are encoded fields of precision prec (the gauge handle must hold
+ * prec) with nrhs right-hand sides; out is parity out_parity, in the other
+ * parity.  No factor kappa.  Asynchronous on stream. */
+wd_status wilson_dslash(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
+                        int32_t dagger, wd_prec prec, int32_t nrhs, void *stream);
+
+/* Even-odd operator (Eq. 2): out_e = in_e - kappa^2 D_eo D_oe in_e (dagger = 1:
+ * the adjoint M_hat^dagger).  tmp_odd is an odd-parity field of the same
+ * precision and nrhs.  Asynchronous on stream. */
+wd_status wilson_mat_pc(const wd_gauge *g, double kappa, void *out, const void *in,
+                        void *tmp_odd, int32_t dagger, wd_prec prec, int32_t nrhs,
+                        void *stream);
+
+/* Normal operator out_e = M_hat^dagger M_hat in_e.  tmp_odd (odd parity) and
+ * tmp_even (even parity) are scratch fields of the same precision and nrhs.
+ * Asynchronous on stream. */
+wd_status mdagm(const wd_gauge *g, double kappa, void *out, const void *in, void *tmp_odd,
+                void *tmp_even, wd_prec prec, int32_t nrhs, void *stream);
+
+/* ---- solvers ------------------------------------------------------------------- */
+
+#define WD_SOLVER_BICGSTAB 0 /* BiCGstab on M_hat (Section 5.1) */
+#define WD_SOLVER_CG 1       /* CG on M_hat^dag M_hat x_e = M_hat^dag b_hat_e (Section 5.1) */
+
+typedef struct {
+  double tol;          /* target ||b - (1 - kappa D) x|| / ||b||, FP64 true residual, > 0 */
+  int32_t maxiter;     /* cap on k + l (iterations plus reliable updates), >= 1 */
+  wd_prec inner;       /* storage precision of the Krylov vectors and of the M_hat applied to
+                          them; WD_FP64 gives the plain double-precision solver */
+  double delta;        /* reliable-update trigger of Algorithm 2: update when |r^| < delta *
+                          max|r^| since the last update; 0 <= delta < 1 (0: update only to
+                          confirm convergence) */
+  int32_t nrhs;        /* right-hand sides solved together, 1..64 (one multi-RHS dslash per hop) */
+  int32_t use_graph;   /* 1: the iteration body is captured once as a hipGraph and replayed
+                          (needs a non-NULL stream) */
+  int32_t check_every; /* reserved, must be 0 or 1 */
+  int32_t x0_given;    /* reserved, must be 0 */
+} wd_solve_params;
+
+typedef struct {
+  int32_t iters;            /* k + l: iterations plus reliable updates (Table 5 convention) */
+  int32_t reliable_updates; /* l */
+  int32_t converged;        /* 1 if the FP64 true residual reached tol */
+  int32_t status;           /* WD_OK, WD_NOT_CONVERGED or WD_EBREAKDOWN for this RHS */
+  double true_rel_resid;    /* ||b_hat - M_hat x_e|| / ||b|| in FP64 at exit; equals the
+                               full-system relative residual (the odd-site residual vanishes) */
+  double seconds;           /* wall time of the whole solve (host clock) */
+  double gflops;            /* nominal rate: 1320 flops per site per dslash plus BLAS-1 flops */
+} wd_solve_info;
+
+/* Device workspace bytes for a solve (all fields, partial sums, scalars). */
+size_t wd_solve_workspace_bytes(const wd_lattice *lat, const wd_solve_params *params,
+                                int32_t solver);
+
+/* Solve (1 - kappa D) x = b for params->nrhs right-hand sides: prepare
+ * b_hat_e = b_e + kappa D_eo b_o, solve M_hat x_e = b_hat_e with reliable
+ * updates in FP64 (Algorithm 2), reconstruct x_o = b_o + kappa D_oe x_e.
+ * x, b: device, canonical full-lattice FP64 [nrhs][V][4][3][2].  The gauge
+ * handle must hold WD_FP64 and params->inner.  Blocks until done.  info is an
+ * array of nrhs records (may be NULL).  Returns WD_OK if every RHS converged,
+ * WD_NOT_CONVERGED if one hit maxiter (x holds the best FP64 iterate),
+ * WD_EBREAKDOWN if the Krylov recurrence broke down for one. */
+wd_status bicgstab_solve(const wd_gauge *g, double kappa, double *x, const double *b,
+                         const wd_solve_params *params, wd_solve_info *info, void *workspace,
+                         size_t ws_bytes, void *stream);
+
+/* Same contract with CG on the normal equations M_hat^dag M_hat. */
+wd_status cg_solve(const wd_gauge *g, double kappa, double *x, const double *b,
+                   const wd_solve_params *params, wd_solve_info *info, void *workspace,
+                   size_t ws_bytes, void *stream);
+
+/* Step API for interleaving several solves (one stream each).  begin
+ * validates, prepares the source and the first residual; step runs up to
+ * n_iters iterations (each followed by its reliable update if triggered) and
+ * sets *done when every RHS has converged, broken down or reached maxiter;
+ * end reconstructs x, fills info[nrhs] and releases the handle. */
+wd_status wd_solver_begin(int32_t solver, const wd_gauge *g, double kappa, double *x,
+                          const double *b, const wd_solve_params *params, void *workspace,
+                          size_t ws_bytes, void *stream, wd_solver **out);
+wd_status wd_solver_step(wd_solver *h, int32_t n_iters, int32_t *done);
+wd_status wd_solver_end(wd_solver *h, wd_solve_info *info);
+
+/* Diagnostics of an in-flight solve: copies, per RHS, the iterated squared
+ * residual |r^|^2, the FP64 true squared residual at the last reliable update
+ * and |b|^2 into out[nrhs][3] (host memory).  Synchronises the solver's stream. */
+wd_status wd_solver_residuals(wd_solver *h, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WD_H */

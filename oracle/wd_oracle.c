@@ -437,7 +437,7 @@ void wdo_f16_to_f32(const uint16_t *in, float *out, int64_t n) {
  *   kind 0 (int16 fixed point): q = rint(v * (32767/norm)), |q| <= 32767,
  *                               decoded as q * (norm/32767);
  *   kind 1 (binary16):          h = f16(v * (1/norm)), decoded as h * norm.
- * A site with norm 0 stores all zeros.
+ * A site with norm 0, or below 2^-100, stores norm 0 and all zeros.
  */
 void wdo_encode_spinor16(int kind, int64_t n, const double *in, uint16_t *q, float *norm) {
   for (int64_t s = 0; s < n; ++s) {
@@ -446,6 +446,9 @@ void wdo_encode_spinor16(int kind, int64_t n, const double *in, uint16_t *q, flo
       v[i] = (float)in[24 * s + i];
       nm = fmaxf(nm, fabsf(v[i]));
     }
+    /* Reading for tiny sites: a norm below 2^-100 would make 32767/norm or
+     * 1/norm overflow binary32, so such a site is stored as zero. */
+    if (nm < 0x1p-100f) nm = 0.0f;
     norm[s] = nm;
     if (nm == 0.0f) { for (int i = 0; i < 24; ++i) q[24 * s + i] = 0; continue; }
     if (kind == 0) {

@@ -1,0 +1,268 @@
+// C ABI of libwdslash.so: argument validation, gauge handles, field
+// encode/decode and the operator entry points.  Every check runs before any
+// launch; no exception crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+wd_status fail(wd_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Chunk arrays are padded to a multiple of 64 sites (one wavefront) so that
+// every chunk array starts 1 KiB-aligned relative to the field base.
+int64_t field_stride(int64_t Vh) { return (Vh + 63) / 64 * 64; }
+
+Geom make_geom(const wd_lattice& lat) {
+  Geom g;
+  int64_t V = 1;
+  for (int m = 0; m < 4; ++m) {
+    g.L[m] = lat.dims[m];
+    V *= lat.dims[m];
+  }
+  g.Lxh = lat.dims[0] / 2;
+  g.Vh = static_cast<int>(V / 2);
+  g.tap = lat.t_antiperiodic ? 1 : 0;
+  g.stride = field_stride(g.Vh);
+  return g;
+}
+
+size_t spinor_field_bytes(const Geom& g, wd_prec p, int nrhs) {
+  size_t b = static_cast<size_t>(nrhs) * spinor_chunks(p) * g.stride * 16;
+  if (is_half(p)) b += static_cast<size_t>(nrhs) * g.stride * 4;
+  return b;
+}
+
+static bool prec_ok(wd_prec p) { return p >= WD_FP64 && p <= WD_HALF_F16; }
+
+// Lattice check: dims even, >= 2, volume within int32 checkerboard indexing.
+static wd_status check_lattice(const wd_lattice* lat) {
+  if (!lat) return fail(WD_EINVAL, "lattice is NULL");
+  int64_t V = 1;
+  for (int m = 0; m < 4; ++m) {
+    const int L = lat->dims[m];
+    if (L < 2 || (L & 1))
+      return fail(WD_EINVAL, "lattice dims must be even and >= 2 (dim " + std::to_string(m) +
+                                 " = " + std::to_string(L) + ")");
+    V *= L;
+  }
+  if (V / 2 > (int64_t)1 << 30) return fail(WD_EINVAL, "lattice volume too large (Vh > 2^30)");
+  if (lat->t_antiperiodic != 0 && lat->t_antiperiodic != 1)
+    return fail(WD_EINVAL, "t_antiperiodic must be 0 or 1");
+  return WD_OK;
+}
+
+static wd_status check_ptr(const void* p, const char* what) {
+  if (!p) return fail(WD_EINVAL, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) % 16)
+    return fail(WD_EINVAL, std::string(what) + " is not 16-byte aligned");
+  return WD_OK;
+}
+
+static wd_status check_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 65535) return fail(WD_EINVAL, "nrhs must be in [1, 65535]");
+  return WD_OK;
+}
+
+static wd_status check_gauge(const wd_gauge* g, wd_prec prec) {
+  if (!g) return fail(WD_EINVAL, "gauge handle is NULL");
+  if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if (!(g->mask & WD_PREC_MASK(prec)) || !g->link[prec])
+    return fail(WD_EINVAL, "gauge handle does not hold the requested precision");
+  return WD_OK;
+}
+
+static wd_status hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return WD_OK;
+  return fail(WD_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static Field field_of(const Geom& g, void* p, int nrhs) {
+  return Field{static_cast<char*>(p), g.stride, nrhs};
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+const char* wd_last_error(void) { return g_last_error.c_str(); }
+
+const char* wd_version(void) { return "wdslash 0.1 (gfx950)"; }
+
+size_t wd_gauge_bytes(const wd_lattice* lat, uint32_t prec_mask) {
+  if (check_lattice(lat) != WD_OK) return 0;
+  if (prec_mask == 0 || (prec_mask & ~0xfu)) return 0;
+  const Geom g = make_geom(*lat);
+  size_t b = 0;
+  for (int p = 0; p < 4; ++p)
+    if (prec_mask & WD_PREC_MASK(p)) b += static_cast<size_t>(8) * g.stride * link_bytes(p);
+  return b;
+}
+
+wd_status wd_gauge_create(const wd_lattice* lat, const double* U_dev, uint32_t prec_mask,
+                          void* dev_buf, size_t bytes, void* stream, wd_gauge** out) {
+  g_last_error.clear();
+  if (!out) return fail(WD_EINVAL, "out is NULL");
+  *out = nullptr;
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if (prec_mask == 0 || (prec_mask & ~0xfu)) return fail(WD_EINVAL, "invalid precision mask");
+  if ((st = check_ptr(U_dev, "U_dev"))) return st;
+  if ((st = check_ptr(dev_buf, "dev_buf"))) return st;
+  const size_t need = wd_gauge_bytes(lat, prec_mask);
+  if (bytes < need)
+    return fail(WD_EINVAL, "dev_buf too small: " + std::to_string(bytes) + " < " + std::to_string(need));
+  wd_gauge* g = new (std::nothrow) wd_gauge;
+  if (!g) return fail(WD_ENOMEM, "host allocation of the gauge handle failed");
+  g->lat = *lat;
+  g->geom = make_geom(*lat);
+  g->mask = prec_mask;
+  char* p = static_cast<char*>(dev_buf);
+  for (int q = 0; q < 4; ++q) {
+    g->link[q] = nullptr;
+    if (prec_mask & WD_PREC_MASK(q)) {
+      g->link[q] = p;
+      p += static_cast<size_t>(8) * g->geom.stride * link_bytes(q);
+    }
+  }
+  st = hip_status(launch_gauge_encode(g, U_dev, static_cast<hipStream_t>(stream)), "gauge encode");
+  if (st) {
+    delete g;
+    return st;
+  }
+  *out = g;
+  return WD_OK;
+}
+
+void wd_gauge_destroy(wd_gauge* g) { delete g; }
+
+size_t wd_spinor_bytes(const wd_lattice* lat, wd_prec prec, int32_t nrhs) {
+  if (check_lattice(lat) != WD_OK || !prec_ok(prec) || check_nrhs(nrhs) != WD_OK) return 0;
+  return spinor_field_bytes(make_geom(*lat), prec, nrhs);
+}
+
+wd_status wd_spinor_encode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, void* field,
+                           const double* canon, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) || (st = check_ptr(canon, "canon")))
+    return st;
+  const Geom g = make_geom(*lat);
+  return hip_status(launch_spinor_encode(g, prec, field_of(g, field, nrhs), canon,
+                                         static_cast<hipStream_t>(stream)),
+                    "spinor encode");
+}
+
+wd_status wd_spinor_decode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, double* canon,
+                           const void* field, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) || (st = check_ptr(canon, "canon")))
+    return st;
+  const Geom g = make_geom(*lat);
+  return hip_status(launch_spinor_decode(g, prec, canon, field_of(g, const_cast<void*>(field), nrhs),
+                                         static_cast<hipStream_t>(stream)),
+                    "spinor decode");
+}
+
+wd_status wd_spinor_encode_full(const wd_lattice* lat, wd_prec prec, int32_t nrhs, int32_t parity,
+                                void* field, const double* canon_full, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if (parity != 0 && parity != 1) return fail(WD_EINVAL, "parity must be 0 or 1");
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) ||
+      (st = check_ptr(canon_full, "canon_full")))
+    return st;
+  const Geom g = make_geom(*lat);
+  return hip_status(launch_spinor_encode_map(g, prec, field_of(g, field, nrhs), canon_full, parity,
+                                             static_cast<hipStream_t>(stream)),
+                    "spinor encode (full lattice)");
+}
+
+wd_status wd_spinor_decode_full(const wd_lattice* lat, wd_prec prec, int32_t nrhs, int32_t parity,
+                                double* canon_full, const void* field, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if (parity != 0 && parity != 1) return fail(WD_EINVAL, "parity must be 0 or 1");
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) ||
+      (st = check_ptr(canon_full, "canon_full")))
+    return st;
+  const Geom g = make_geom(*lat);
+  return hip_status(launch_spinor_decode_map(g, prec, canon_full,
+                                             field_of(g, const_cast<void*>(field), nrhs), parity,
+                                             static_cast<hipStream_t>(stream)),
+                    "spinor decode (full lattice)");
+}
+
+wd_status wilson_dslash(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
+                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_gauge(g, prec);
+  if (st) return st;
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(out, "out")) || (st = check_ptr(in, "in"))) return st;
+  if (out_parity != 0 && out_parity != 1) return fail(WD_EINVAL, "out_parity must be 0 or 1");
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  if (out == in) return fail(WD_EINVAL, "out and in must not alias");
+  const Geom& geo = g->geom;
+  return hip_status(launch_dslash(g, prec, field_of(geo, out, nrhs), field_of(geo, const_cast<void*>(in), nrhs),
+                                  out_parity, dagger, nullptr, 0.0, static_cast<hipStream_t>(stream)),
+                    "wilson_dslash");
+}
+
+wd_status wilson_mat_pc(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
+                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_gauge(g, prec);
+  if (st) return st;
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(out, "out")) || (st = check_ptr(in, "in")) ||
+      (st = check_ptr(tmp_odd, "tmp_odd")))
+    return st;
+  if (!std::isfinite(kappa) || kappa <= 0) return fail(WD_EINVAL, "kappa must be finite and > 0");
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  if (out == in || tmp_odd == in || tmp_odd == out) return fail(WD_EINVAL, "fields must not alias");
+  const Geom& geo = g->geom;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Field fo = field_of(geo, out, nrhs), fi = field_of(geo, const_cast<void*>(in), nrhs);
+  Field ft = field_of(geo, tmp_odd, nrhs);
+  hipError_t e = launch_dslash(g, prec, ft, fi, 1, dagger, nullptr, 0.0, s);
+  if (e == hipSuccess) e = launch_dslash(g, prec, fo, ft, 0, dagger, &fi, -kappa * kappa, s);
+  return hip_status(e, "wilson_mat_pc");
+}
+
+wd_status mdagm(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
+                void* tmp_even, wd_prec prec, int32_t nrhs, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_gauge(g, prec);
+  if (st) return st;
+  if ((st = check_ptr(tmp_even, "tmp_even"))) return st;
+  if (tmp_even == in || tmp_even == out || tmp_even == tmp_odd)
+    return fail(WD_EINVAL, "fields must not alias");
+  st = wilson_mat_pc(g, kappa, tmp_even, in, tmp_odd, 0, prec, nrhs, stream);
+  if (st) return st;
+  return wilson_mat_pc(g, kappa, out, tmp_even, tmp_odd, 1, prec, nrhs, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Conversions between the caller's canonical FP64 layouts and the device
+// field formats: gauge links to 12-real rows (Appendix A.1) in each storage
+// precision, spinors to site-coalesced chunk arrays with, for the 16-bit
+// formats, a per-site norm (Section 4.6).
+#include "wd_device.h"
+
+namespace wd {
+
+struct SiteMap {
+  int L[4];
+  int Lxh;
+  int Vh;
+};
+
+// lex index of checkerboard site cb of parity p.
+__device__ __forceinline__ int64_t lex_of(const SiteMap& m, int cb, int p) {
+  int rest = cb / m.Lxh;
+  const int xh = cb - rest * m.Lxh;
+  const int y = rest % m.L[1];
+  rest /= m.L[1];
+  const int z = rest % m.L[2];
+  const int t = rest / m.L[2];
+  const int x = 2 * xh + ((p + y + z + t) & 1);
+  return x + (int64_t)m.L[0] * (y + (int64_t)m.L[1] * (z + (int64_t)m.L[2] * t));
+}
+
+static SiteMap site_map(const Geom& g) {
+  SiteMap m;
+  for (int k = 0; k < 4; ++k) m.L[k] = g.L[k];
+  m.Lxh = g.Lxh;
+  m.Vh = g.Vh;
+  return m;
+}
+
+// ---- gauge ------------------------------------------------------------------------
+// One thread per (site cb, parity, mu): rows a, b of U[lex][mu] into every
+// precision of the mask.  16-bit: int16 q = rint(u * 32767) or binary16 u.
+__global__ void gauge_encode_kernel(SiteMap m, const double* __restrict__ U, int64_t stride,
+                                    char* f64, char* f32, char* i16, char* h16) {
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int par = blockIdx.y >> 2, mu = blockIdx.y & 3;
+  if (cb >= m.Vh) return;
+  const int64_t lex = lex_of(m, cb, par);
+  const double* u = U + (lex * 4 + mu) * 18;  // rows a, b are the first 12 reals
+  double v[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = u[k];
+  if (f64) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      reinterpret_cast<double2*>(const_cast<char*>(link_chunk<SF64>(f64, stride, par, mu, k)))[cb] =
+          make_double2(v[2 * k], v[2 * k + 1]);
+  }
+  if (f32) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      reinterpret_cast<float4*>(const_cast<char*>(link_chunk<SF32>(f32, stride, par, mu, k)))[cb] =
+          make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2], (float)v[4 * k + 3]);
+  }
+  if (i16) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float a = fminf(fmaxf(rintf((float)v[4 * k + 2 * j] * 32767.0f), -32767.0f), 32767.0f);
+        float b = fminf(fmaxf(rintf((float)v[4 * k + 2 * j + 1] * 32767.0f), -32767.0f), 32767.0f);
+        w[j] = (uint32_t)(uint16_t)(int16_t)a | ((uint32_t)(uint16_t)(int16_t)b << 16);
+      }
+      reinterpret_cast<uint2*>(const_cast<char*>(link_chunk<SI16>(i16, stride, par, mu, k)))[cb] =
+          make_uint2(w[0], w[1]);
+    }
+  }
+  if (h16) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        w[j] = (uint32_t)f_to_h16((float)v[4 * k + 2 * j]) |
+               ((uint32_t)f_to_h16((float)v[4 * k + 2 * j + 1]) << 16);
+      reinterpret_cast<uint2*>(const_cast<char*>(link_chunk<SF16>(h16, stride, par, mu, k)))[cb] =
+          make_uint2(w[0], w[1]);
+    }
+  }
+}
+
+hipError_t launch_gauge_encode(const wd_gauge* g, const double* U, hipStream_t s) {
+  SiteMap m = site_map(g->geom);
+  const int block = 256;
+  dim3 grid((m.Vh + block - 1) / block, 8);
+  gauge_encode_kernel<<<grid, block, 0, s>>>(
+      m, U, g->geom.stride, static_cast<char*>(g->link[WD_FP64]), static_cast<char*>(g->link[WD_FP32]),
+      static_cast<char*>(g->link[WD_HALF_I16]), static_cast<char*>(g->link[WD_HALF_F16]));
+  return hipGetLastError();
+}
+
+// ---- spinors ----------------------------------------------------------------------
+// full_parity < 0: canonical array is a parity array [nrhs][Vh][24];
+// full_parity = p: canonical array is a full lattice [nrhs][V][24] and the
+// field holds its parity-p sites.
+template <class S>
+__global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __restrict__ canon,
+                                     int full_parity) {
+  using R = typename S::real;
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (cb >= m.Vh) return;
+  const int64_t V = 2 * (int64_t)m.Vh;
+  const double* src = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
+                                        : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
+  Spinor<R> s;
+#pragma unroll
+  for (int n = 0; n < 12; ++n) s.v[n / 3][n % 3] = {static_cast<R>(src[2 * n]), static_cast<R>(src[2 * n + 1])};
+  store_spinor<S>(f, r, cb, s);
+}
+
+template <class S>
+__global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict__ canon,
+                                     int full_parity) {
+  using R = typename S::real;
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (cb >= m.Vh) return;
+  const int64_t V = 2 * (int64_t)m.Vh;
+  double* dst = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
+                                  : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
+  Spinor<R> s;
+  load_spinor<S>(f, r, cb, s);
+#pragma unroll
+  for (int n = 0; n < 12; ++n) {
+    dst[2 * n] = static_cast<double>(s.v[n / 3][n % 3].re);
+    dst[2 * n + 1] = static_cast<double>(s.v[n / 3][n % 3].im);
+  }
+}
+
+template <class S>
+static hipError_t enc_typed(const Geom& g, Field f, const double* canon, int full_parity,
+                            hipStream_t s) {
+  const int block = 256;
+  dim3 grid((g.Vh + block - 1) / block, f.nrhs);
+  spinor_encode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
+                                                 canon, full_parity);
+  return hipGetLastError();
+}
+
+template <class S>
+static hipError_t dec_typed(const Geom& g, double* canon, Field f, int full_parity, hipStream_t s) {
+  const int block = 256;
+  dim3 grid((g.Vh + block - 1) / block, f.nrhs);
+  spinor_decode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
+                                                 canon, full_parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
+                                    int full_parity, hipStream_t s) {
+  switch (p) {
+    case WD_FP64: return enc_typed<SF64>(g, f, canon, full_parity, s);
+    case WD_FP32: return enc_typed<SF32>(g, f, canon, full_parity, s);
+    case WD_HALF_I16: return enc_typed<SI16>(g, f, canon, full_parity, s);
+    case WD_HALF_F16: return enc_typed<SF16>(g, f, canon, full_parity, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
+                                    int full_parity, hipStream_t s) {
+  switch (p) {
+    case WD_FP64: return dec_typed<SF64>(g, canon, f, full_parity, s);
+    case WD_FP32: return dec_typed<SF32>(g, canon, f, full_parity, s);
+    case WD_HALF_I16: return dec_typed<SI16>(g, canon, f, full_parity, s);
+    case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,
+                                hipStream_t s) {
+  return launch_spinor_encode_map(g, p, f, canon, -1, s);
+}
+
+hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f, hipStream_t s) {
+  return launch_spinor_decode_map(g, p, canon, f, -1, s);
+}
+
+}  // namespace wd

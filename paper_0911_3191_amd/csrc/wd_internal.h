@@ -1,0 +1,150 @@
+// Internal declarations shared by the host and device translation units of
+// libwdslash.so.  Not part of the public ABI (include/wd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "wd.h"
+
+namespace wd {
+
+// Lattice geometry as the kernels see it.  Every field of one lattice uses the
+// same per-chunk site stride `stride` (>= Vh, padded, see field_stride).
+struct Geom {
+  int L[4];     // Lx, Ly, Lz, Lt
+  int Lxh;      // Lx / 2
+  int Vh;       // sites per parity
+  int tap;      // antiperiodic in t
+  int64_t stride;
+};
+
+Geom make_geom(const wd_lattice& lat);
+int64_t field_stride(int64_t Vh);
+
+// Bytes of one real in each storage precision and the number of 16-byte
+// chunks a site's 24 spinor reals occupy.
+inline int spinor_chunks(wd_prec p) { return p == WD_FP64 ? 12 : (p == WD_FP32 ? 6 : 3); }
+inline bool is_half(wd_prec p) { return p == WD_HALF_I16 || p == WD_HALF_F16; }
+// Bytes per link (12 reals).
+inline int link_bytes(wd_prec p) { return p == WD_FP64 ? 96 : (p == WD_FP32 ? 48 : 24); }
+
+// A parity spinor field: nrhs right-hand sides, chunk arrays of `stride`
+// 16-byte elements each, laid out [rhs][chunk][site]; 16-bit formats append
+// a binary32 norm array [rhs][site] after all chunks.
+struct Field {
+  char* ptr;
+  int64_t stride;
+  int nrhs;
+};
+
+size_t spinor_field_bytes(const Geom& g, wd_prec p, int nrhs);
+
+}  // namespace wd
+
+struct wd_gauge {
+  wd_lattice lat;
+  wd::Geom geom;
+  uint32_t mask;
+  void* link[4];  // per precision: [parity][mu][chunk][site]
+};
+
+namespace wd {
+
+// ---- launchers (defined in the .hip files; all asynchronous on `s`) -------------
+constexpr int kMaxDotHost = 4;  // doubles per partial record
+enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3 };
+
+// Full argument set of one dslash launch.  out = D in, or, with xpay set,
+// out = *xpay + a * D in; with xpay and dot set, per-block FP64 partials of
+// the dot products named by DotMode go to partials[rhs][block][4].  RHS whose
+// active flag is 0 are skipped.
+struct DslashArgs {
+  Field out{}, in{};
+  int out_parity = 0, dagger = 0;
+  const Field* xpay = nullptr;
+  double a = 0.0;
+  int dot = DOT_NONE;
+  const Field* y = nullptr;
+  double* partials = nullptr;
+  const int* active = nullptr;
+};
+hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
+int dslash_blocks(const Geom& g);
+
+// out_p = D_{p,1-p} in (dagger: adjoint).  When xpay_src is non-null:
+// out = xpay_src + a * D in (xpay_src has parity p, same precision).
+hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int out_parity,
+                         int dagger, const Field* xpay_src, double a, hipStream_t s);
+
+hipError_t launch_gauge_encode(const wd_gauge* g, const double* U, hipStream_t s);
+
+// canonical parity spinors [nrhs][Vh][24] <-> field
+hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,
+                                hipStream_t s);
+hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f,
+                                hipStream_t s);
+// full_parity = p: the canonical array is a full lattice [nrhs][V][24] and the
+// field holds (or provides) its parity-p sites; full_parity < 0: parity array.
+hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
+                                    int full_parity, hipStream_t s);
+hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
+                                    int full_parity, hipStream_t s);
+
+// ---- solver state on the device --------------------------------------------------
+// Per-RHS FP64 scalars (complex ones take two slots: re, im).
+enum ScalarSlot {
+  SC_RHO = 0,      // rho = <r~, r^> (BiCGstab, complex) or |r^|^2 (CG)
+  SC_RHOP = 2,     // previous rho
+  SC_ALPHA = 4,    // alpha (complex for BiCGstab)
+  SC_OMEGA = 6,    // omega (BiCGstab)
+  SC_R2 = 8,       // |r^|^2 of the iterated residual
+  SC_RTRUE2 = 9,   // |b_hat - M_hat x|^2 at the last reliable update (FP64)
+  SC_MMAX = 10,    // max |r^| since the last reliable update (Algorithm 2's M)
+  SC_B2 = 11,      // |b|^2 of the full-lattice source
+  SC_TOLN = 12,    // CG: target on the normal-equation residual
+  SC_BETA = 13,    // CG: beta
+  SC_BNORM = 14,   // |b| of the caller's source (the solve runs on b / |b|)
+  SC_COUNT = 16
+};
+enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_COUNT = 4 };
+enum FinStage {
+  FIN_B2_FIRST, FIN_B2_ADD, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
+  FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO
+};
+
+hipError_t blas_bicg_p(const Geom& g, wd_prec pr, Field p, Field r, Field v, const double* sc,
+                       const int* mask, hipStream_t s);
+hipError_t blas_bicg_s(const Geom& g, wd_prec pr, Field r, Field v, const double* sc,
+                       const int* mask, hipStream_t s);
+hipError_t blas_bicg_xr(const Geom& g, wd_prec pr, Field x, Field r, Field p, Field t, Field rt,
+                        const double* sc, const int* mask, double* partials, hipStream_t s);
+hipError_t blas_cg_xr(const Geom& g, wd_prec pr, Field x, Field r, Field p, Field q,
+                      const double* sc, const int* mask, double* partials, hipStream_t s);
+hipError_t blas_cg_p(const Geom& g, wd_prec pr, Field p, Field r, const double* sc,
+                     const int* mask, hipStream_t s);
+hipError_t blas_convert(const Geom& g, wd_prec dst_prec, Field dst, wd_prec src_prec, Field src,
+                        const int* mask, hipStream_t s);
+hipError_t blas_zero(const Geom& g, wd_prec pr, Field f, const int* mask, hipStream_t s);
+hipError_t blas_norm2(const Geom& g, wd_prec pr, Field f, const int* mask, double* partials,
+                      hipStream_t s);
+hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int* mask, hipStream_t s);
+hipError_t blas_residual(const Geom& g, Field r64, Field b64, const int* mask, double* partials,
+                         hipStream_t s);
+hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s);
+hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
+                         const int* mask, double* partials, hipStream_t s);
+hipError_t solver_finalize(int stage, int nrhs, int nb, const double* partials, double* sc, int* fl,
+                           int* active, int* rumask, const int* mask, double delta, double tol,
+                           hipStream_t s);
+hipError_t solver_cg_tighten(int nrhs, double* sc, const int* fl, const int* mask, double tol,
+                             hipStream_t s);
+hipError_t solver_init_flags(int nrhs, int* fl, int* active, int* rumask, hipStream_t s);
+
+// ---- error reporting ------------------------------------------------------------
+void set_error(const std::string& msg);
+wd_status fail(wd_status code, const std::string& msg);
+
+}  // namespace wd

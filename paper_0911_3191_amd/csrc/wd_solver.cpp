@@ -1,0 +1,530 @@
+// Solver drivers: BiCGstab on M_hat and CG on M_hat^dag M_hat (Section 5.1)
+// with reliable updates (Section 5.3, Algorithm 2): the Krylov iteration runs
+// with its vectors and its M_hat in the inner storage precision; whenever the
+// iterated residual has dropped by delta against its maximum since the last
+// update (or reaches the target), the inner solution is added to the FP64
+// accumulator, the FP64 residual b_hat - M_hat x is recomputed with the FP64
+// gauge field and replaces the iterated one, and the inner solution restarts
+// from zero.  The Krylov recurrences (p, v, rho, alpha, omega) are kept.
+//
+// All scalars live in device memory and are produced by finalize kernels, so
+// the host only reads a few flags per iteration (reliable-update trigger,
+// convergence, breakdown).  The iteration body can be captured once into a
+// hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Workspace layout shared by wd_solve_workspace_bytes and the drivers.
+struct Layout {
+  size_t hi_field, lo_field;
+  int n_hi_even, n_hi_odd, n_lo_even, n_lo_odd;
+  size_t partials, scalars, flags, masks;
+  size_t total;
+};
+
+static Layout layout(const Geom& g, int kind, wd_prec inner, int nrhs) {
+  Layout L;
+  L.hi_field = align256(spinor_field_bytes(g, WD_FP64, nrhs));
+  L.lo_field = align256(spinor_field_bytes(g, inner, nrhs));
+  // high precision: b_hat, x, r (+ the normal-equation residual for CG) and an odd temporary
+  L.n_hi_even = (kind == WD_SOLVER_CG) ? 4 : 3;
+  L.n_hi_odd = 1;
+  // low precision: BiCGstab r^, r~, p, v, t, x^; CG r^, p, q, w, x^; plus an odd temporary
+  L.n_lo_even = (kind == WD_SOLVER_CG) ? 5 : 6;
+  L.n_lo_odd = 1;
+  const int nb = (g.Vh + 255) / 256;
+  L.partials = align256(sizeof(double) * kMaxDotHost * nb * (size_t)nrhs);
+  L.scalars = align256(sizeof(double) * SC_COUNT * (size_t)nrhs);
+  L.flags = align256(sizeof(int) * FL_COUNT * (size_t)nrhs);
+  L.masks = align256(sizeof(int) * 2 * (size_t)nrhs);
+  L.total = (L.n_hi_even + L.n_hi_odd) * L.hi_field + (L.n_lo_even + L.n_lo_odd) * L.lo_field +
+            L.partials + L.scalars + L.flags + L.masks;
+  return L;
+}
+
+}  // namespace wd
+
+struct wd_solver {
+  int kind;
+  const wd_gauge* g;
+  wd::Geom geom;
+  double kappa;
+  wd_solve_params prm;
+  hipStream_t s;
+  double* x_out;
+  const double* b_in;
+  int nrhs, nb;
+  wd::Field bhat, x, r, rn, to64;
+  wd::Field rh, rt, p, v, t, xh, to;  // CG uses v as q and t as w; rt unused
+  double* partials;
+  double* sc;
+  int* fl;
+  int* active;
+  int* rumask;
+  int* h_fl;       // pinned host copy of the flags
+  double* h_sc;    // pinned host copy of the scalars
+  std::vector<int> iters, rus, status, done_rhs;
+  std::string note;  // breakdown details for wd_last_error
+  int loops;
+  bool finished;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  bool graph_ready;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace wd {
+
+static hipError_t dslash_into(wd_solver* h, wd_prec prec, const Field& out, const Field& in,
+                              int parity, int dagger, const Field* xpay, double a, int dot,
+                              const Field* y, const int* mask) {
+  DslashArgs d;
+  d.out = out;
+  d.in = in;
+  d.out_parity = parity;
+  d.dagger = dagger;
+  d.xpay = xpay;
+  d.a = a;
+  d.dot = dot;
+  d.y = y;
+  d.partials = h->partials;
+  d.active = mask;
+  return launch_dslash_ex(h->g, prec, d, h->s);
+}
+
+// out_e = in_e - kappa^2 D_eo D_oe in_e (dagger: the adjoint), optional fused dot.
+static hipError_t mhat_into(wd_solver* h, wd_prec prec, const Field& out, const Field& in,
+                            const Field& tmp_odd, int dagger, int dot, const Field* y,
+                            const int* mask) {
+  hipError_t e = dslash_into(h, prec, tmp_odd, in, 1, dagger, nullptr, 0.0, DOT_NONE, nullptr, mask);
+  if (e != hipSuccess) return e;
+  return dslash_into(h, prec, out, tmp_odd, 0, dagger, &in, -h->kappa * h->kappa, dot, y, mask);
+}
+
+static hipError_t fin(wd_solver* h, int stage, const int* mask) {
+  return solver_finalize(stage, h->nrhs, h->nb, h->partials, h->sc, h->fl, h->active, h->rumask,
+                         mask, h->prm.delta, h->prm.tol, h->s);
+}
+
+#define WD_TRY(expr)                         \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+// One Krylov iteration in the inner precision, all active RHS.
+static hipError_t iteration_body(wd_solver* h) {
+  const Geom& g = h->geom;
+  const wd_prec P = h->prm.inner;
+  const int* act = h->active;
+  if (h->kind == WD_SOLVER_BICGSTAB) {
+    WD_TRY(blas_bicg_p(g, P, h->p, h->rh, h->v, h->sc, act, h->s));
+    WD_TRY(mhat_into(h, P, h->v, h->p, h->to, 0, DOT_YO, &h->rt, act));  // v = M p, <r~, v>
+    WD_TRY(fin(h, FIN_BICG_ALPHA, act));
+    WD_TRY(blas_bicg_s(g, P, h->rh, h->v, h->sc, act, h->s));           // s = r - alpha v
+    WD_TRY(mhat_into(h, P, h->t, h->rh, h->to, 0, DOT_OX, nullptr, act));  // t = M s, <t,s>, |t|^2
+    WD_TRY(fin(h, FIN_BICG_OMEGA, act));
+    WD_TRY(blas_bicg_xr(g, P, h->xh, h->rh, h->p, h->t, h->rt, h->sc, act, h->partials, h->s));
+    WD_TRY(fin(h, FIN_BICG_ITER, act));
+  } else {
+    // w = M p (|w|^2), q = M^dag w, x^ += alpha p, r^ -= alpha q
+    WD_TRY(mhat_into(h, P, h->t, h->p, h->to, 0, DOT_OO, nullptr, act));
+    WD_TRY(fin(h, FIN_CG_ALPHA, act));
+    WD_TRY(mhat_into(h, P, h->v, h->t, h->to, 1, DOT_NONE, nullptr, act));
+    WD_TRY(blas_cg_xr(g, P, h->xh, h->rh, h->p, h->v, h->sc, act, h->partials, h->s));
+    WD_TRY(fin(h, FIN_CG_ITER, act));
+  }
+  return hipSuccess;
+}
+
+// FP64 r = b_hat - M_hat x for the RHS in mask, then the convergence test.
+static hipError_t true_residual(wd_solver* h, const int* mask) {
+  WD_TRY(mhat_into(h, WD_FP64, h->r, h->x, h->to64, 0, DOT_NONE, nullptr, mask));
+  WD_TRY(blas_residual(h->geom, h->r, h->bhat, mask, h->partials, h->s));
+  WD_TRY(fin(h, FIN_TRUE, mask));
+  return hipSuccess;
+}
+
+// Re-seed the inner residual from the FP64 one (and zero x^) for the RHS in rumask.
+static hipError_t reseed(wd_solver* h, bool first) {
+  const Geom& g = h->geom;
+  const wd_prec P = h->prm.inner;
+  if (h->kind == WD_SOLVER_BICGSTAB) {
+    if (first) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, h->r, h->rumask, h->s));  // r~ = r_0
+    WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->r, &h->rt, h->rumask, h->partials, h->s));
+    WD_TRY(fin(h, first ? FIN_BICG_INIT : FIN_RHO, h->rumask));
+  } else {
+    if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
+    // normal-equation residual M_hat^dag r in FP64
+    WD_TRY(mhat_into(h, WD_FP64, h->rn, h->r, h->to64, 1, DOT_NONE, nullptr, h->rumask));
+    WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->rn, nullptr, h->rumask, h->partials, h->s));
+    WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask));
+    if (first) WD_TRY(blas_convert(g, P, h->p, P, h->rh, h->rumask, h->s));  // p = r^
+  }
+  return hipSuccess;
+}
+
+static hipError_t reliable_update(wd_solver* h) {
+  WD_TRY(blas_accum(h->geom, h->prm.inner, h->x, h->xh, h->rumask, h->s));  // x += x^
+  WD_TRY(true_residual(h, h->rumask));                                       // r = b - M x
+  WD_TRY(reseed(h, false));                                                  // r^ = r, x^ = 0
+  return hipSuccess;
+}
+
+static const char* const kStageNames[] = {"b2", "b2+", "true residual", "rho", "bicg init",
+                                          "alpha", "omega", "bicg iter", "cg init", "cg alpha",
+                                          "cg iter", "cg rho"};
+
+static void note_breakdown(wd_solver* h, int k) {
+  const int st = h->h_fl[k * FL_COUNT + FL_BREAK] - 1;
+  const char* name = (st >= 0 && st < 12) ? kStageNames[st] : "?";
+  char buf[160];
+  snprintf(buf, sizeof(buf), " rhs %d at %s (iteration %d, |r^|^2 %.3e, rho %.3e)", k, name,
+           h->iters[k], h->h_sc[k * SC_COUNT + SC_R2], h->h_sc[k * SC_COUNT + SC_RHO]);
+  h->note += buf;
+}
+
+static hipError_t read_flags(wd_solver* h) {
+  WD_TRY(hipMemcpyAsync(h->h_fl, h->fl, sizeof(int) * FL_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s));
+  WD_TRY(hipMemcpyAsync(h->h_sc, h->sc, sizeof(double) * SC_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s));
+  return hipStreamSynchronize(h->s);
+}
+
+static hipError_t prepare(wd_solver* h) {
+  const Geom& g = h->geom;
+  const int n = h->nrhs;
+  WD_TRY(solver_init_flags(n, h->fl, h->active, h->rumask, h->s));
+  // b_e -> r, b_o -> to64; |b|^2 = |b_e|^2 + |b_o|^2
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s));
+  WD_TRY(blas_norm2(g, WD_FP64, h->r, nullptr, h->partials, h->s));
+  WD_TRY(fin(h, FIN_B2_FIRST, nullptr));
+  WD_TRY(blas_norm2(g, WD_FP64, h->to64, nullptr, h->partials, h->s));
+  WD_TRY(fin(h, FIN_B2_ADD, nullptr));
+  // solve for b / |b| (unit source per RHS); x is scaled back at reconstruction
+  WD_TRY(blas_scale_bnorm(g, h->r, h->sc, 1, h->s));
+  WD_TRY(blas_scale_bnorm(g, h->to64, h->sc, 1, h->s));
+  // b_hat = b_e + kappa D_eo b_o
+  WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_NONE, nullptr, nullptr));
+  WD_TRY(blas_zero(g, WD_FP64, h->x, nullptr, h->s));
+  // r = b_hat - M_hat 0 via the same path as every reliable update
+  WD_TRY(true_residual(h, nullptr));
+  WD_TRY(blas_zero(g, h->prm.inner, h->p, nullptr, h->s));
+  WD_TRY(blas_zero(g, h->prm.inner, h->v, nullptr, h->s));
+  WD_TRY(reseed(h, true));
+  return hipSuccess;
+}
+
+// x_o = b_o + kappa D_oe x_e, then both parities into the caller's x.
+static hipError_t reconstruct(wd_solver* h) {
+  const Geom& g = h->geom;
+  WD_TRY(blas_scale_bnorm(g, h->x, h->sc, 0, h->s));  // undo the unit-source scaling
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s));
+  WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, &h->to64, h->kappa, DOT_NONE, nullptr, nullptr));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s));
+  return hipStreamSynchronize(h->s);
+}
+
+static wd_status hip_fail(hipError_t e, const char* where) {
+  return fail(WD_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+namespace {
+
+wd_status validate(int kind, const wd_gauge* g, double kappa, const void* x, const void* b,
+                   const wd_solve_params* prm, const void* ws, size_t ws_bytes) {
+  if (kind != WD_SOLVER_BICGSTAB && kind != WD_SOLVER_CG) return fail(WD_EINVAL, "unknown solver");
+  if (!g) return fail(WD_EINVAL, "gauge handle is NULL");
+  if (!prm) return fail(WD_EINVAL, "params is NULL");
+  if (!std::isfinite(kappa) || kappa <= 0) return fail(WD_EINVAL, "kappa must be finite and > 0");
+  if (!(prm->tol > 0) || !std::isfinite(prm->tol)) return fail(WD_EINVAL, "tol must be finite and > 0");
+  if (prm->maxiter < 1) return fail(WD_EINVAL, "maxiter must be >= 1");
+  if (!(prm->delta >= 0.0 && prm->delta < 1.0)) return fail(WD_EINVAL, "delta must satisfy 0 <= delta < 1");
+  if (prm->nrhs < 1 || prm->nrhs > 64) return fail(WD_EINVAL, "nrhs must be in [1, 64]");
+  if (prm->inner < WD_FP64 || prm->inner > WD_HALF_F16) return fail(WD_EINVAL, "unknown inner precision");
+  if (prm->x0_given != 0) return fail(WD_EUNSUPPORTED, "x0_given is not supported");
+  if (prm->check_every < 0 || prm->check_every > 1) return fail(WD_EINVAL, "check_every must be 0 or 1");
+  if (!(g->mask & WD_PREC_MASK(WD_FP64)) || !(g->mask & WD_PREC_MASK(prm->inner)))
+    return fail(WD_EINVAL, "gauge handle must hold FP64 and the inner precision");
+  for (const void* p : {x, b, ws}) {
+    if (!p) return fail(WD_EINVAL, "x, b and workspace must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(p) % 256) return fail(WD_EINVAL, "x, b and workspace must be 256-byte aligned");
+  }
+  if (x == b) return fail(WD_EINVAL, "x and b must not alias");
+  const Layout L = layout(g->geom, kind, prm->inner, prm->nrhs);
+  if (ws_bytes < L.total)
+    return fail(WD_EINVAL, "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(L.total));
+  return WD_OK;
+}
+
+double flops_per_iter(int kind) { return kind == WD_SOLVER_CG ? 5616.0 : 6336.0; }
+double flops_per_update(int kind) { return kind == WD_SOLVER_CG ? 5616.0 : 2784.0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t wd_solve_workspace_bytes(const wd_lattice* lat, const wd_solve_params* prm, int32_t solver) {
+  if (!lat || !prm || (solver != WD_SOLVER_BICGSTAB && solver != WD_SOLVER_CG)) return 0;
+  if (wd_gauge_bytes(lat, 1) == 0) return 0;
+  if (prm->nrhs < 1 || prm->nrhs > 64 || prm->inner < WD_FP64 || prm->inner > WD_HALF_F16) return 0;
+  return layout(make_geom(*lat), solver, prm->inner, prm->nrhs).total;
+}
+
+wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, double* x, const double* b,
+                          const wd_solve_params* prm, void* workspace, size_t ws_bytes, void* stream,
+                          wd_solver** out) {
+  set_error("");
+  if (!out) return fail(WD_EINVAL, "out is NULL");
+  *out = nullptr;
+  wd_status st = validate(solver, g, kappa, x, b, prm, workspace, ws_bytes);
+  if (st) return st;
+  wd_solver* h = new (std::nothrow) wd_solver();
+  if (!h) return fail(WD_ENOMEM, "host allocation failed");
+  h->kind = solver;
+  h->g = g;
+  h->geom = g->geom;
+  h->kappa = kappa;
+  h->prm = *prm;
+  h->s = static_cast<hipStream_t>(stream);
+  h->x_out = x;
+  h->b_in = b;
+  h->nrhs = prm->nrhs;
+  h->nb = (h->geom.Vh + 255) / 256;
+  const Layout L = layout(h->geom, solver, prm->inner, prm->nrhs);
+  char* p = static_cast<char*>(workspace);
+  auto take_hi = [&]() { Field f{p, h->geom.stride, h->nrhs}; p += L.hi_field; return f; };
+  auto take_lo = [&]() { Field f{p, h->geom.stride, h->nrhs}; p += L.lo_field; return f; };
+  h->bhat = take_hi();
+  h->x = take_hi();
+  h->r = take_hi();
+  h->rn = (solver == WD_SOLVER_CG) ? take_hi() : Field{nullptr, 0, 0};
+  h->to64 = take_hi();
+  h->rh = take_lo();
+  h->p = take_lo();
+  h->v = take_lo();
+  h->t = take_lo();
+  h->xh = take_lo();
+  h->rt = (solver == WD_SOLVER_BICGSTAB) ? take_lo() : Field{nullptr, 0, 0};
+  h->to = take_lo();
+  h->partials = reinterpret_cast<double*>(p);
+  p += L.partials;
+  h->sc = reinterpret_cast<double*>(p);
+  p += L.scalars;
+  h->fl = reinterpret_cast<int*>(p);
+  p += L.flags;
+  h->active = reinterpret_cast<int*>(p);
+  h->rumask = h->active + h->nrhs;
+  h->iters.assign(h->nrhs, 0);
+  h->rus.assign(h->nrhs, 0);
+  h->status.assign(h->nrhs, WD_NOT_CONVERGED);
+  h->done_rhs.assign(h->nrhs, 0);
+  h->graph_ready = false;
+  h->finished = false;
+  h->loops = 0;
+  h->t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->h_fl), sizeof(int) * FL_COUNT * h->nrhs);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->h_sc), sizeof(double) * SC_COUNT * h->nrhs);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "pinned host buffer");
+  }
+  e = prepare(h);
+  if (e == hipSuccess) e = read_flags(h);
+  if (e != hipSuccess) {
+    (void)hipHostFree(h->h_fl);
+    (void)hipHostFree(h->h_sc);
+    delete h;
+    return hip_fail(e, "solver prepare");
+  }
+  for (int k = 0; k < h->nrhs; ++k) {
+    if (!std::isfinite(h->h_sc[k * SC_COUNT + SC_B2])) {
+      (void)hipHostFree(h->h_fl);
+      (void)hipHostFree(h->h_sc);
+      delete h;
+      return fail(WD_EINVAL, "source contains NaN or Inf");
+    }
+    if (h->h_fl[k * FL_COUNT + FL_CONV]) {
+      h->done_rhs[k] = 1;
+      h->status[k] = WD_OK;
+    }
+  }
+  *out = h;
+  return WD_OK;
+}
+
+wd_status wd_solver_step(wd_solver* h, int32_t n_iters, int32_t* done) {
+  set_error("");
+  if (!h) return fail(WD_EINVAL, "solver handle is NULL");
+  if (n_iters < 1) return fail(WD_EINVAL, "n_iters must be >= 1");
+  for (int it = 0; it < n_iters && !h->finished; ++it) {
+    bool any = false;
+    for (int k = 0; k < h->nrhs; ++k) any |= !h->done_rhs[k];
+    if (!any || h->loops >= h->prm.maxiter) {
+      h->finished = true;
+      break;
+    }
+    hipError_t e = hipSuccess;
+    if (h->prm.use_graph && h->s) {
+      if (!h->graph_ready) {
+        e = hipStreamBeginCapture(h->s, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+          hipError_t eb = iteration_body(h);
+          e = hipStreamEndCapture(h->s, &h->graph);
+          if (eb != hipSuccess) e = eb;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) h->graph_ready = true;
+      }
+      if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->s);
+    } else {
+      e = iteration_body(h);
+    }
+    if (e == hipSuccess) e = read_flags(h);
+    if (e != hipSuccess) return hip_fail(e, "solver iteration");
+    ++h->loops;
+    bool any_ru = false;
+    for (int k = 0; k < h->nrhs; ++k) {
+      if (h->done_rhs[k]) continue;
+      ++h->iters[k];
+      if (h->h_fl[k * FL_COUNT + FL_BREAK]) {
+        h->done_rhs[k] = 1;
+        h->status[k] = WD_EBREAKDOWN;
+        note_breakdown(h, k);
+        continue;
+      }
+      if (h->h_fl[k * FL_COUNT + FL_RU]) any_ru = true;
+    }
+    if (any_ru) {
+      e = reliable_update(h);
+      if (e == hipSuccess) e = read_flags(h);
+      if (e != hipSuccess) return hip_fail(e, "reliable update");
+      ++h->loops;
+      for (int k = 0; k < h->nrhs; ++k) {
+        if (h->done_rhs[k] || !h->h_fl[k * FL_COUNT + FL_RU]) continue;
+        ++h->iters[k];
+        ++h->rus[k];
+        if (h->h_fl[k * FL_COUNT + FL_CONV]) {
+          h->done_rhs[k] = 1;
+          h->status[k] = WD_OK;
+        } else if (h->h_fl[k * FL_COUNT + FL_BREAK]) {
+          h->done_rhs[k] = 1;
+          h->status[k] = WD_EBREAKDOWN;
+          note_breakdown(h, k);
+        }
+      }
+    }
+    if (h->kind == WD_SOLVER_CG) {
+      // p = r^ + beta p for the RHS still iterating (after any reliable update)
+      e = blas_cg_p(h->geom, h->prm.inner, h->p, h->rh, h->sc, h->active, h->s);
+      if (e != hipSuccess) return hip_fail(e, "cg p update");
+    }
+  }
+  bool any = false;
+  for (int k = 0; k < h->nrhs; ++k) any |= !h->done_rhs[k];
+  if (!any || h->loops >= h->prm.maxiter) h->finished = true;
+  if (done) *done = h->finished ? 1 : 0;
+  return WD_OK;
+}
+
+wd_status wd_solver_residuals(wd_solver* h, double* out) {
+  set_error("");
+  if (!h || !out) return fail(WD_EINVAL, "solver handle or out is NULL");
+  hipError_t e = read_flags(h);
+  if (e != hipSuccess) return hip_fail(e, "wd_solver_residuals");
+  for (int k = 0; k < h->nrhs; ++k) {
+    out[3 * k] = h->h_sc[k * SC_COUNT + SC_R2];
+    out[3 * k + 1] = h->h_sc[k * SC_COUNT + SC_RTRUE2];
+    out[3 * k + 2] = h->h_sc[k * SC_COUNT + SC_B2];
+  }
+  return WD_OK;
+}
+
+wd_status wd_solver_end(wd_solver* h, wd_solve_info* info) {
+  set_error("");
+  if (!h) return fail(WD_EINVAL, "solver handle is NULL");
+  hipError_t e = reconstruct(h);
+  if (e == hipSuccess) e = read_flags(h);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - h->t0).count();
+  wd_status result = WD_OK;
+  if (e != hipSuccess) result = hip_fail(e, "solver end");
+  for (int k = 0; k < h->nrhs && result != WD_EDEVICE; ++k) {
+    const double* s = h->h_sc + k * SC_COUNT;
+    const double rel = (s[SC_B2] > 0) ? std::sqrt(s[SC_RTRUE2] / s[SC_B2]) : 0.0;
+    if (info) {
+      info[k].iters = h->iters[k];
+      info[k].reliable_updates = h->rus[k];
+      info[k].converged = (h->status[k] == WD_OK) ? 1 : 0;
+      info[k].status = h->status[k];
+      info[k].true_rel_resid = rel;
+      info[k].seconds = secs;
+      const double fl = (h->iters[k] - h->rus[k]) * flops_per_iter(h->kind) +
+                        h->rus[k] * flops_per_update(h->kind);
+      info[k].gflops = secs > 0 ? fl * h->geom.Vh / secs * 1e-9 : 0.0;
+    }
+    if (h->status[k] == WD_EBREAKDOWN) result = WD_EBREAKDOWN;
+    else if (h->status[k] != WD_OK && result == WD_OK) result = WD_NOT_CONVERGED;
+  }
+  if (h->graph_ready) {
+    (void)hipGraphExecDestroy(h->gexec);
+    (void)hipGraphDestroy(h->graph);
+  }
+  (void)hipHostFree(h->h_fl);
+  (void)hipHostFree(h->h_sc);
+  const std::string note = h->note;
+  delete h;
+  if (result == WD_NOT_CONVERGED) set_error("maxiter reached before the target residual");
+  if (result == WD_EBREAKDOWN) set_error("Krylov recurrence broke down:" + note);
+  return result;
+}
+
+static wd_status solve(int kind, const wd_gauge* g, double kappa, double* x, const double* b,
+                       const wd_solve_params* prm, wd_solve_info* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+  wd_solver* h = nullptr;
+  wd_status st = wd_solver_begin(kind, g, kappa, x, b, prm, ws, ws_bytes, stream, &h);
+  if (st) return st;
+  int done = 0;
+  while (!done) {
+    st = wd_solver_step(h, 1 << 20, &done);
+    if (st) {
+      std::string msg = wd_last_error();
+      wd_solver_end(h, nullptr);
+      return fail(st, msg);
+    }
+  }
+  return wd_solver_end(h, info);
+}
+
+wd_status bicgstab_solve(const wd_gauge* g, double kappa, double* x, const double* b,
+                         const wd_solve_params* params, wd_solve_info* info, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  return solve(WD_SOLVER_BICGSTAB, g, kappa, x, b, params, info, workspace, ws_bytes, stream);
+}
+
+wd_status cg_solve(const wd_gauge* g, double kappa, double* x, const double* b,
+                   const wd_solve_params* params, wd_solve_info* info, void* workspace,
+                   size_t ws_bytes, void* stream) {
+  return solve(WD_SOLVER_CG, g, kappa, x, b, params, info, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+"""The C ABI library loads, exports every function include/wd.h declares, and
+rejects invalid arguments before touching the device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\([^;{]*\)\s*;", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_0911_3191_amd as wd
+    return wd.lib()
+
+
+def test_header_declares_the_path_entry_points():
+    names = declared_functions()
+    for n in ("wilson_dslash", "mdagm", "wilson_mat_pc", "wd_gauge_create", "wd_spinor_encode"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_validation_rejects_bad_lattices_and_arguments(lib):
+    import paper_0911_3191_amd as wd
+    assert wd.wd_gauge_bytes(wd.lattice((4, 4, 4, 3)), 1) == 0       # odd dim
+    assert wd.wd_gauge_bytes(wd.lattice((0, 4, 4, 4)), 1) == 0       # empty
+    assert wd.wd_gauge_bytes(wd.lattice((4, 4, 4, 4)), 0) == 0       # empty mask
+    assert wd.wd_spinor_bytes(wd.lattice((4, 4, 4, 4)), "fp32", 0) == 0
+    n64 = wd.wd_spinor_bytes(wd.lattice((4, 4, 4, 4)), "fp64", 1)
+    assert n64 == 12 * 128 * 16
+    assert wd.wd_spinor_bytes(wd.lattice((4, 4, 4, 4)), "i16", 2) == 2 * (3 * 128 * 16 + 128 * 4)
+    # NULL gauge handle and NULL fields are refused with WD_EINVAL, no launch
+    st = lib.wilson_dslash(None, None, None, 0, 0, 0, 1, None)
+    assert st == -1
+    assert b"NULL" in lib.wd_last_error()
+    lat = wd.lattice((4, 4, 4, 4))
+    h = ctypes.c_void_p()
+    st = lib.wd_gauge_create(ctypes.byref(lat), ctypes.c_void_p(16), 1, ctypes.c_void_p(32), 10,
+                             None, ctypes.byref(h))
+    assert st == -1 and b"too small" in lib.wd_last_error()
+    st = lib.wd_gauge_create(ctypes.byref(lat), ctypes.c_void_p(17), 1, ctypes.c_void_p(32), 1 << 30,
+                             None, ctypes.byref(h))
+    assert st == -1 and b"aligned" in lib.wd_last_error()
+    bad = wd.lattice((4, 4, 4, 5))
+    st = lib.wd_spinor_encode(ctypes.byref(bad), 0, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert st == -1 and b"even" in lib.wd_last_error()

@@ -1,0 +1,160 @@
+"""Parity of the HIP dslash, M_hat and M_hat^dag M_hat with the FP64 oracle.
+
+Bars (relative L2 over the output field): 1e-13 in FP64, 1e-6 in FP32, 2e-3 in
+the two 16-bit storage formats.  Lattices span several 256-site workgroups and
+ragged tails; multi-RHS results must equal the single-RHS ones bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import wdinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0911_3191_amd as wd  # noqa: E402
+from gpu_helpers import Setup, rel_l2  # noqa: E402
+
+TOL = {"fp64": 1e-13, "fp32": 1e-6, "i16": 2e-3, "f16": 2e-3}
+PRECS = ["fp64", "fp32", "i16", "f16"]
+SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 6, 10), (10, 6, 4, 8), (8, 8, 8, 8)]
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda d: "x".join(map(str, d)))
+def setup(request):
+    dims = request.param
+    U = wdinputs.gauge_random(dims, 0.5, 17)
+    return Setup(dims, U)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_dslash_matches_oracle(setup, prec, dagger):
+    s = setup
+    psi = wdinputs.spinor_gaussian(s.dims, 5)
+    pe, po = oracle.split(s.dims, psi)
+    for p in (0, 1):
+        fin = s.encode_full(prec, psi, 1 - p)
+        fout = s.field(prec)
+        wd.wilson_dslash(s.gauge, fout, fin, p, dagger, prec)
+        got = s.decode(prec, fout)
+        ref = oracle.dslash_parity(s.dims, s.U, po if p == 0 else pe, p, dagger=bool(dagger))
+        err = rel_l2(got, ref)
+        assert err <= TOL[prec], f"{prec} parity {p} dagger {dagger}: rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_periodic_t(prec):
+    dims = (4, 4, 6, 6)
+    U = wdinputs.gauge_random(dims, 0.3, 23)
+    s = Setup(dims, U, tap=False)
+    psi = wdinputs.spinor_gaussian(dims, 24)
+    _, po = oracle.split(dims, psi)
+    fin = s.encode_full(prec, psi, 1)
+    fout = s.field(prec)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec)
+    ref = oracle.dslash_parity(dims, U, po, 0, antiperiodic_t=False)
+    assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_mat_pc_and_mdagm(setup, prec, dagger):
+    s = setup
+    kappa = 0.124
+    psi = wdinputs.spinor_gaussian(s.dims, 6)
+    pe, _ = oracle.split(s.dims, psi)
+    fin = s.encode_parity(prec, pe)
+    fout, tmp = s.field(prec), s.field(prec)
+    wd.wilson_mat_pc(s.gauge, kappa, fout, fin, tmp, dagger, prec)
+    ref = oracle.mhat(s.dims, s.U, kappa, pe, dagger=bool(dagger))
+    assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec]
+    if dagger == 0:
+        tmpe = s.field(prec)
+        wd.mdagm(s.gauge, kappa, fout, fin, tmp, tmpe, prec)
+        ref2 = oracle.mhat(s.dims, s.U, kappa, oracle.mhat(s.dims, s.U, kappa, pe), dagger=True)
+        assert rel_l2(s.decode(prec, fout), ref2) <= 2 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_multi_rhs_equals_single_rhs_bitwise(prec):
+    dims = (6, 4, 6, 10)
+    U = wdinputs.gauge_random(dims, 0.5, 31)
+    s = Setup(dims, U)
+    srcs = wdinputs.spinor_gaussian(dims, 32, nrhs=3)
+    fin = s.encode_full(prec, srcs, 1, nrhs=3)
+    fout = s.field(prec, 3)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 3)
+    batch = s.decode(prec, fout, 3)
+    for k in range(3):
+        f1 = s.encode_full(prec, srcs[k], 1)
+        o1 = s.field(prec)
+        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        assert np.array_equal(s.decode(prec, o1), batch[k])
+
+
+@pytest.mark.parametrize("kind", ["i16", "f16"])
+def test_spinor16_encode_is_bit_exact_with_oracle(kind):
+    dims = (4, 4, 4, 6)
+    s = Setup(dims, wdinputs.gauge_unit(dims))
+    rng = np.random.default_rng(3)
+    psi = rng.normal(size=(s.Vh, 4, 3, 2)) * np.exp(rng.normal(size=(s.Vh, 1, 1, 1)) * 2)
+    psi[5] = 0.0
+    f = s.encode_parity(kind, psi)
+    got = s.decode(kind, f)
+    q, nm = oracle.encode_spinor16(kind, psi)
+    ref = oracle.decode_spinor16(kind, q, nm)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kind", ["i16", "f16"])
+def test_16bit_dslash_against_oracle_on_quantised_inputs(kind):
+    """Feed the oracle the 16-bit-rounded links and spinor: what remains is FP32
+    arithmetic plus one output rounding, bounded per site by the output norm."""
+    dims = (6, 4, 6, 10)
+    U = wdinputs.gauge_random(dims, 0.5, 41)
+    s = Setup(dims, U)
+    Uq = oracle.decode_link16(kind, oracle.encode_link16(kind, U))
+    uq = Uq[..., 0] + 1j * Uq[..., 1]
+    c = np.conj(np.cross(uq[..., 0, :], uq[..., 1, :]))  # the third row the kernel rebuilds
+    Uq[..., 2, :, 0], Uq[..., 2, :, 1] = c.real, c.imag
+    psi = wdinputs.spinor_gaussian(dims, 42)
+    _, po = oracle.split(dims, psi)
+    q, nm = oracle.encode_spinor16(kind, po)
+    po_q = oracle.decode_spinor16(kind, q, nm)
+    fin = s.encode_parity(kind, po)
+    fout = s.field(kind)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, kind)
+    got = s.decode(kind, fout).reshape(s.Vh, 24)
+    ref = oracle.dslash_parity(dims, Uq, po_q, 0).reshape(s.Vh, 24)
+    site_norm = np.abs(ref).max(axis=1, keepdims=True)
+    lsb = site_norm / 32767 if kind == "i16" else site_norm * 2.0 ** -11
+    bound = 0.5 * lsb * 1.01 + 64 * 6e-8 * site_norm
+    ratio = np.abs(got - ref) / bound
+    i, j = np.unravel_index(np.argmax(ratio), ratio.shape)
+    assert ratio.max() <= 1.0, (f"site {i} comp {j}: got {got[i, j]!r} ref {ref[i, j]!r} "
+                                f"norm {site_norm[i, 0]!r} ratio {ratio.max():.3f}")
+
+
+def test_accuracy_cdf_uniform_vector():
+    """Accuracy metric of Eq. 3 with eta in [0, 1] and random SU(3) links: the
+    largest deviation of M_hat from the FP64 CPU result, in units of the
+    precision's unit roundoff times the output scale."""
+    dims = (8, 8, 8, 8)
+    U = wdinputs.gauge_random(dims, 2.0, 51)
+    s = Setup(dims, U)
+    eta = wdinputs.spinor_uniform(dims, 52)
+    ee, _ = oracle.split(dims, eta)
+    ref = oracle.mhat(dims, U, 0.12, ee)
+    scale = np.abs(ref).max()
+    ulp = {"fp64": 2.0 ** -52, "fp32": 2.0 ** -23}
+    for prec in ("fp64", "fp32"):
+        fin = s.encode_parity(prec, ee)
+        fout, tmp = s.field(prec), s.field(prec)
+        wd.wilson_mat_pc(s.gauge, 0.12, fout, fin, tmp, 0, prec)
+        dev = np.abs(s.decode(prec, fout) - ref).max() / (scale * ulp[prec])
+        assert dev < 200, f"{prec}: first deviation at {dev:.1f} ulp"

@@ -346,6 +346,20 @@ def test_spinor16_encoding_properties(kind):
 
 
 @pytest.mark.parametrize("kind", ["i16", "f16"])
+def test_spinor16_tiny_sites_are_stored_as_zero(kind):
+    """Sites whose norm is below 2^-100 (where 32767/norm would overflow binary32)
+    are stored as zero; just above the threshold the scale stays finite."""
+    psi = np.zeros((3, 4, 3, 2))
+    psi[0, 1, 2, 0] = 3e-39    # binary32 denormal
+    psi[1, 0, 0, 1] = 2.0 ** -101
+    psi[2, 3, 1, 0] = 2.0 ** -99
+    q, nm = oracle.encode_spinor16(kind, psi)
+    assert nm[0] == 0 and nm[1] == 0 and not q[:2].any()
+    dec = oracle.decode_spinor16(kind, q, nm)
+    assert np.all(np.isfinite(dec)) and dec[2, 3, 1, 0] == 2.0 ** -99
+
+
+@pytest.mark.parametrize("kind", ["i16", "f16"])
 def test_link16_encoding_properties(kind):
     U = wdinputs.gauge_random((2, 2, 2, 2), 0.5, 3)
     q = oracle.encode_link16(kind, U)
