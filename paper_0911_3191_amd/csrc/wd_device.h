@@ -131,6 +131,33 @@ __device__ __forceinline__ void load_spinor(const FieldView& f, int r, int64_t i
   (void)sizeof(R);
 }
 
+// Same as load_spinor, but 16-bit values come back in units of the site's
+// norm (no multiply) with the factor returned in `scale`; for FP32/FP64
+// fields scale is 1.
+template <class S>
+__device__ __forceinline__ void load_spinor_raw(const FieldView& f, int r, int64_t i,
+                                                Spinor<typename S::real>& s, typename S::real& scale) {
+  if constexpr (S::prec == WD_FP64 || S::prec == WD_FP32) {
+    load_spinor<S>(f, r, i, s);
+    scale = typename S::real(1);
+  } else {
+    const float nm = norm_base(f, r)[i];
+    scale = (S::prec == WD_HALF_I16) ? nm / 32767.0f : nm;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 c = reinterpret_cast<const uint4*>(chunk_base<S>(f, r, k))[i];
+      uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint16_t lo = (uint16_t)(w[j] & 0xffffu), hi = (uint16_t)(w[j] >> 16);
+        const int n = 4 * k + j;
+        if constexpr (S::prec == WD_HALF_I16) s.v[n / 3][n % 3] = {(float)(int16_t)lo, (float)(int16_t)hi};
+        else s.v[n / 3][n % 3] = {h16_to_f(lo), h16_to_f(hi)};
+      }
+    }
+  }
+}
+
 // Encode 24 reals of the arithmetic type into one site of the field.
 template <class S>
 __device__ __forceinline__ void store_spinor(const FieldView& f, int r, int64_t i,

@@ -1,12 +1,13 @@
 // Wilson-Dirac hopping term on one parity (Section 3, Eq. 1), for the
 // storage formats FP64, FP32, int16 + norm and binary16 + norm.
 //
-// One thread computes one output site of parity p for one right-hand side:
-// for each direction mu it gathers the two neighbours of the opposite parity,
-// projects each onto its rank-2 spin subspace (6 complex numbers), multiplies
-// by the 12-real link rebuilt to 3x3 (U forward, U^dagger backward), expands
-// the result back to 4 spins and accumulates.  The t boundary sign is applied
-// to the hop, never folded into the stored link.
+// One thread computes one output site of parity p for NR right-hand sides:
+// for each direction mu it loads and rebuilds the link once (12 reals ->
+// 3x3, Appendix A.1), then for each of its RHS gathers the neighbour of the
+// opposite parity, projects it onto its rank-2 spin subspace (6 complex
+// numbers), multiplies by U (forward) or U^dagger (backward), expands back to
+// 4 spins and accumulates.  The t-boundary sign is applied to the hop, never
+// folded into the stored link.
 //
 // Spin projection in the DeGrand-Rossi basis (Appendix B): every gamma_mu is
 // off-diagonal in 2x2 blocks, gamma_mu = [[0, A_mu], [A_mu^dag, 0]], so
@@ -15,12 +16,24 @@
 // adjoint swaps them).  Each A_mu has one entry per row, a power of i:
 //   A_x = [[0, i], [i, 0]],  A_y = [[0, -1], [1, 0]],
 //   A_z = [[i, 0], [0, -i]], A_t = [[1, 0], [0, 1]].
+//
+// 16-bit neighbours are projected and multiplied in units of their own site
+// norm; the norm enters once, in the accumulating FMA.
+//
+// Work distribution (XCD-aware): the 8 XCDs of the chip each own one z-slab
+// of the lattice and sweep it with t slowest, so the two t-neighbour slices a
+// site needs were fetched by the same XCD shortly before (its own L2 holds
+// them for single-RHS FP32/FP64).  Hardware assigns workgroup b to XCD b % 8;
+// within an XCD, consecutive workgroups take consecutive slab positions, and
+// the RHS groups of one site block are adjacent so their link loads hit L2.
+// Lattices with Lz not divisible by 8 fall back to one contiguous
+// checkerboard range per XCD.
 #include "wd_device.h"
 #include "wd_reduce.h"
 
 namespace wd {
 
-// Row k of A_mu has its entry in column PERM_k with value i^PH_k.
+// Row k of A_mu has its entry in column P_k with value i^PH_k.
 template <int MU>
 struct Gamma;
 template <> struct Gamma<0> { static constexpr int P0 = 1, P1 = 0, PH0 = 1, PH1 = 1; };
@@ -28,21 +41,174 @@ template <> struct Gamma<1> { static constexpr int P0 = 1, P1 = 0, PH0 = 2, PH1 
 template <> struct Gamma<2> { static constexpr int P0 = 0, P1 = 1, PH0 = 1, PH1 = 3; };
 template <> struct Gamma<3> { static constexpr int P0 = 0, P1 = 1, PH0 = 0, PH1 = 0; };
 
-struct GeomView {
-  int L[4];
-  int Lxh;
-  int Vh;
-  int tap;
-  int64_t stride;  // chunk stride of every field and of the links
+// n / d for n < 2^31 with a precomputed multiplier (round-up method).
+struct FastDiv {
+  uint32_t m, s;
 };
-
-__device__ __forceinline__ int cb_index(const GeomView& g, int x, int y, int z, int t) {
-  return (x >> 1) + g.Lxh * (y + g.L[1] * (z + g.L[2] * t));
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
+static FastDiv make_fastdiv(uint32_t d) {
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1;
+  return FastDiv{static_cast<uint32_t>(m), s};
 }
 
-// Accumulate one hop: acc += eta * (1 + s gamma_mu) (W psi), W = U or U^dagger.
+struct DslashGeom {
+  int L[4];
+  int Lxh, Vh, tap;
+  int64_t stride;       // chunk stride of every field and of the links
+  FastDiv div_lxh;      // / Lxh
+  FastDiv div_ly;       // / Ly
+  FastDiv div_lz;       // / Lz
+  int slab;             // 1: z-slab mapping, 0: contiguous range per XCD
+  int slab_t_sites;     // sites of one parity in one slab at fixed t (plane * Lz / 8)
+  FastDiv div_slab_t;   // / slab_t_sites
+  int site_blocks;      // site blocks per XCD (slab) or in total (contiguous)
+  int ngroups;          // RHS groups
+  int nrhs;
+};
+
+// ---- buffer loads --------------------------------------------------------------
+// Gathers use raw buffer loads: a per-RHS descriptor (base in SGPRs), the
+// site offset as a 32-bit VGPR and the chunk offset as an SGPR, which keeps
+// 64-bit address arithmetic out of the hot loop.  Out-of-range offsets read
+// zero instead of faulting.
+constexpr int kBufWord3 = 0x00020000;  // raw, untyped buffer (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+
+template <class S>
+struct SpinorBuf {
+  __amdgpu_buffer_rsrc_t chunks;  // [chunk][site] of one RHS
+  __amdgpu_buffer_rsrc_t norms;   // [site] of one RHS (16-bit formats)
+  uint32_t chunk_bytes;           // stride * 16
+};
+
+template <class S>
+__device__ __forceinline__ SpinorBuf<S> spinor_buf(const FieldView& f, int r) {
+  SpinorBuf<S> b;
+  b.chunk_bytes = (uint32_t)(f.stride * 16);
+  b.chunks = make_rsrc(chunk_base<S>(f, r, 0), b.chunk_bytes * S::NCH);
+  if constexpr (kHalf<S>) b.norms = make_rsrc(norm_base(f, r), (uint32_t)(f.stride * 4));
+  else b.norms = b.chunks;
+  return b;
+}
+
+__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ uint2 bload8(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// Neighbour spinor of one RHS in units of its site norm (scale returned).
+template <class S>
+__device__ __forceinline__ void gather_spinor(const SpinorBuf<S>& b, int i, Spinor<typename S::real>& s,
+                                              typename S::real& scale) {
+  const uint32_t vo = (uint32_t)i * 16u;
+  if constexpr (S::prec == WD_FP64) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 c = __builtin_bit_cast(double2, bload16(b.chunks, vo, k * b.chunk_bytes));
+      s.v[k / 3][k % 3] = {c.x, c.y};
+    }
+    scale = 1.0;
+  } else if constexpr (S::prec == WD_FP32) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 c = __builtin_bit_cast(float4, bload16(b.chunks, vo, k * b.chunk_bytes));
+      s.v[(2 * k) / 3][(2 * k) % 3] = {c.x, c.y};
+      s.v[(2 * k + 1) / 3][(2 * k + 1) % 3] = {c.z, c.w};
+    }
+    scale = 1.0f;
+  } else {
+    const float nm = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.norms, (uint32_t)i * 4u, 0, 0));
+    scale = (S::prec == WD_HALF_I16) ? nm * (1.0f / 32767.0f) : nm;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint4 c = bload16(b.chunks, vo, k * b.chunk_bytes);
+      const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint16_t lo = (uint16_t)(w[j] & 0xffffu), hi = (uint16_t)(w[j] >> 16);
+        const int n = 4 * k + j;
+        if constexpr (S::prec == WD_HALF_I16) s.v[n / 3][n % 3] = {(float)(int16_t)lo, (float)(int16_t)hi};
+        else s.v[n / 3][n % 3] = {h16_to_f(lo), h16_to_f(hi)};
+      }
+    }
+  }
+}
+
+// Rows a, b of link (par, mu) at site i, third row rebuilt as (a x b)^*.
+template <class S>
+__device__ __forceinline__ void gather_link(const char* links, int64_t stride, int par, int mu, int i,
+                                            Link<typename S::real>& L) {
+  using R = typename S::real;
+  constexpr int N = LinkChunks<S>::N, B = LinkChunks<S>::BYTES;
+  const uint32_t cbytes = (uint32_t)(stride * B);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(link_chunk<S>(links, stride, par, mu, 0), cbytes * N);
+  const uint32_t vo = (uint32_t)i * (uint32_t)B;
+  cx<R> e[6];
+  if constexpr (S::prec == WD_FP64) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double2 c = __builtin_bit_cast(double2, bload16(rs, vo, k * cbytes));
+      e[k] = {c.x, c.y};
+    }
+  } else if constexpr (S::prec == WD_FP32) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 c = __builtin_bit_cast(float4, bload16(rs, vo, k * cbytes));
+      e[2 * k] = {c.x, c.y};
+      e[2 * k + 1] = {c.z, c.w};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint2 c = bload8(rs, vo, k * cbytes);
+      const uint32_t w[2] = {c.x, c.y};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const uint16_t lo = (uint16_t)(w[j] & 0xffffu), hi = (uint16_t)(w[j] >> 16);
+        if constexpr (S::prec == WD_HALF_I16)
+          e[2 * k + j] = {(float)(int16_t)lo * (1.0f / 32767.0f), (float)(int16_t)hi * (1.0f / 32767.0f)};
+        else
+          e[2 * k + j] = {h16_to_f(lo), h16_to_f(hi)};
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    L.u[0][b] = e[b];
+    L.u[1][b] = e[3 + b];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    L.u[2][j] = conj(L.u[0][j1] * L.u[1][j2] - L.u[0][j2] * L.u[1][j1]);
+  }
+}
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a * b and acc + conj(a) * b as four FMAs
+template <typename R>
+__device__ __forceinline__ cx<R> cmac(cx<R> acc, cx<R> a, cx<R> b) {
+  return {fmar(-a.im, b.im, fmar(a.re, b.re, acc.re)), fmar(a.im, b.re, fmar(a.re, b.im, acc.im))};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cmacc(cx<R> acc, cx<R> a, cx<R> b) {
+  return {fmar(a.im, b.im, fmar(a.re, b.re, acc.re)), fmar(-a.im, b.re, fmar(a.re, b.im, acc.im))};
+}
+
+// Accumulate one hop: acc += scale * (1 + s gamma_mu) (W psi), W = U or U^dagger
+// (scale carries the 16-bit norm and the t-boundary sign).
 template <int MU, int S, bool DAG_LINK, typename R>
-__device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const Link<R>& U, bool flip) {
+__device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const Link<R>& U, R scale) {
   using G = Gamma<MU>;
   constexpr int sh = (S < 0) ? 2 : 0;  // multiplying by s = -1 is a factor i^2
   cx<R> h[2][3];
@@ -51,62 +217,84 @@ __device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const 
     h[0][c] = psi.v[0][c] + iph<G::PH0 + sh>(psi.v[2 + G::P0][c]);
     h[1][c] = psi.v[1][c] + iph<G::PH1 + sh>(psi.v[2 + G::P1][c]);
   }
-  cx<R> w[2][3];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
+    const int lo = 2 + (k == 0 ? G::P0 : G::P1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      cx<R> s;
+      cx<R> w = {R(0), R(0)};
       if constexpr (!DAG_LINK) {
-        s = U.u[a][0] * h[k][0];
-        s = s + U.u[a][1] * h[k][1];
-        s = s + U.u[a][2] * h[k][2];
+        w = cmac(w, U.u[a][0], h[k][0]);
+        w = cmac(w, U.u[a][1], h[k][1]);
+        w = cmac(w, U.u[a][2], h[k][2]);
       } else {
-        s = cmulc(U.u[0][a], h[k][0]);
-        s = s + cmulc(U.u[1][a], h[k][1]);
-        s = s + cmulc(U.u[2][a], h[k][2]);
+        w = cmacc(w, U.u[0][a], h[k][0]);
+        w = cmacc(w, U.u[1][a], h[k][1]);
+        w = cmacc(w, U.u[2][a], h[k][2]);
       }
-      w[k][a] = flip ? cx<R>{-s.re, -s.im} : s;
+      // upper spin k gets w; lower spin P_k gets s conj(A[k][P_k]) w = i^(sh - PH_k) w
+      acc.v[k][a] = acc.v[k][a] + scale * w;
+      const cx<R> wl = (k == 0) ? iph<sh - G::PH0 + 4>(w) : iph<sh - G::PH1 + 4>(w);
+      acc.v[lo][a] = acc.v[lo][a] + scale * wl;
     }
-  }
-  // lower spin P_k of the result = s * conj(A[k][P_k]) * w_k = i^(sh - PH_k) w_k
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    acc.v[0][a] = acc.v[0][a] + w[0][a];
-    acc.v[1][a] = acc.v[1][a] + w[1][a];
-    acc.v[2 + G::P0][a] = acc.v[2 + G::P0][a] + iph<sh - G::PH0 + 4>(w[0][a]);
-    acc.v[2 + G::P1][a] = acc.v[2 + G::P1][a] + iph<sh - G::PH1 + 4>(w[1][a]);
   }
 }
 
-template <class S, int MU, bool DAGGER>
-__device__ __forceinline__ void hop_pair(Spinor<typename S::real>& acc, const GeomView& g,
-                                         const char* links, int64_t stride, const FieldView& in,
-                                         int r, int p, int cb, const int (&X)[4]) {
+// Both hops of direction MU for the NR right-hand sides of this thread.
+template <class S, int MU, bool DAGGER, int NR>
+__device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
+                                         const char* __restrict__ links, const SpinorBuf<S> (&in)[NR],
+                                         const bool (&on)[NR], int p, int cb, int xh, int row,
+                                         const int (&X)[4]) {
   using R = typename S::real;
+  // neighbour checkerboard indices; row = y + Ly (z + Lz t)
+  int nf, nb;
+  bool flip_f = false, flip_b = false;
+  if constexpr (MU == 0) {
+    const int xf = (X[0] + 1 == g.L[0]) ? 0 : X[0] + 1;
+    const int xb = (X[0] == 0) ? g.L[0] - 1 : X[0] - 1;
+    nf = (xf >> 1) + g.Lxh * row;
+    nb = (xb >> 1) + g.Lxh * row;
+  } else {
+    int step = 1;
+    if constexpr (MU >= 2) step *= g.L[1];
+    if constexpr (MU == 3) step *= g.L[2];
+    const int rf = (X[MU] + 1 == g.L[MU]) ? row - (g.L[MU] - 1) * step : row + step;
+    const int rb = (X[MU] == 0) ? row + (g.L[MU] - 1) * step : row - step;
+    nf = xh + g.Lxh * rf;
+    nb = xh + g.Lxh * rb;
+    if constexpr (MU == 3) {
+      flip_f = g.tap && (X[3] == g.L[3] - 1);
+      flip_b = g.tap && (X[3] == 0);
+    }
+  }
   // forward: (1 - gamma_mu) U_x^mu psi(x + mu); adjoint: (1 + gamma_mu)
   {
-    int Y[4] = {X[0], X[1], X[2], X[3]};
-    Y[MU] = (X[MU] + 1 == g.L[MU]) ? 0 : X[MU] + 1;
-    const bool flip = (MU == 3) && g.tap && (X[3] == g.L[3] - 1);
-    const int nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
-    Spinor<R> psi;
-    load_spinor<S>(in, r, nb, psi);
     Link<R> U;
-    load_link<S>(links, stride, p, MU, cb, U);
-    hop<MU, DAGGER ? +1 : -1, false>(acc, psi, U, flip);
+    gather_link<S>(links, g.stride, p, MU, cb, U);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (!on[k]) continue;
+      Spinor<R> psi;
+      R sc;
+      gather_spinor<S>(in[k], nf, psi, sc);
+      if (flip_f) sc = -sc;
+      hop<MU, DAGGER ? +1 : -1, false>(acc[k], psi, U, sc);
+    }
   }
   // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
   {
-    int Y[4] = {X[0], X[1], X[2], X[3]};
-    Y[MU] = (X[MU] == 0) ? g.L[MU] - 1 : X[MU] - 1;
-    const bool flip = (MU == 3) && g.tap && (X[3] == 0);
-    const int nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
-    Spinor<R> psi;
-    load_spinor<S>(in, r, nb, psi);
     Link<R> U;
-    load_link<S>(links, stride, 1 - p, MU, nb, U);
-    hop<MU, DAGGER ? -1 : +1, true>(acc, psi, U, flip);
+    gather_link<S>(links, g.stride, 1 - p, MU, nb, U);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (!on[k]) continue;
+      Spinor<R> psi;
+      R sc;
+      gather_spinor<S>(in[k], nb, psi, sc);
+      if (flip_b) sc = -sc;
+      hop<MU, DAGGER ? -1 : +1, true>(acc[k], psi, U, sc);
+    }
   }
 }
 
@@ -115,163 +303,237 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real>& acc, const Ge
 //   DOT_YO: <y, out>                 (complex; BiCGstab <r~, v>)
 //   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
 //   DOT_OO: |out|^2                  (CG |M p|^2)
-// Right-hand sides whose active flag is 0 are skipped (the block returns).
-template <class S, bool DAGGER, bool XPAY, int DOT>
-__global__ void __launch_bounds__(kBlock) dslash_kernel(GeomView g, const char* __restrict__ links,
+// Right-hand sides whose active flag is 0 are skipped.
+template <class S, bool DAGGER, bool XPAY, int DOT, int NR>
+__global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
                                                        FieldView ys, typename S::real a, int p,
                                                        const int* __restrict__ active,
                                                        double* __restrict__ partials) {
   using R = typename S::real;
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = cb < g.Vh;
-  Spinor<R> acc;
+  // ---- which sites and RHS this workgroup owns ----
+  const int xcd = blockIdx.x & 7;
+  const int j = blockIdx.x >> 3;
+  int site_block, group, pid, cb;
+  bool valid;
+  if (g.slab) {
+    site_block = j / g.ngroups;
+    group = j - site_block * g.ngroups;
+    if (site_block >= g.site_blocks) return;
+    pid = xcd * g.site_blocks + site_block;
+    const int s_local = site_block * blockDim.x + threadIdx.x;  // position in this XCD's slab
+    valid = s_local < (g.Vh >> 3);
+    const int t = (int)fdiv((uint32_t)s_local, g.div_slab_t);
+    const int off = s_local - t * g.slab_t_sites;
+    cb = t * (g.slab_t_sites << 3) + xcd * g.slab_t_sites + off;
+  } else {
+    const int per = (g.site_blocks * g.ngroups + 7) >> 3;
+    const int L = xcd * per + j;
+    if (j >= per || L >= g.site_blocks * g.ngroups) return;
+    site_block = L / g.ngroups;
+    group = L - site_block * g.ngroups;
+    pid = site_block;
+    cb = site_block * blockDim.x + threadIdx.x;
+    valid = cb < g.Vh;
+  }
+  int rhs[NR];
+  bool on[NR];
+  bool any = false;
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int k = 0; k < NR; ++k) {
+    rhs[k] = group * NR + k;
+    on[k] = rhs[k] < g.nrhs && (!active || active[rhs[k]]);
+    any |= on[k];
+  }
+  if (!any) return;
+
+  Spinor<R> acc[NR];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc.v[s][c] = {R(0), R(0)};
-  Spinor<R> x;
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[k].v[s][c] = {R(0), R(0)};
   if (valid) {
     // coordinates of the output site (cb, parity p)
-    int rest = cb / g.Lxh;
-    const int xh = cb - rest * g.Lxh;
+    const int row = (int)fdiv((uint32_t)cb, g.div_lxh);
+    const int xh = cb - row * g.Lxh;
     int X[4];
-    X[1] = rest % g.L[1];
-    rest /= g.L[1];
-    X[2] = rest % g.L[2];
-    X[3] = rest / g.L[2];
+    const int zt = (int)fdiv((uint32_t)row, g.div_ly);
+    X[1] = row - zt * g.L[1];
+    X[3] = (int)fdiv((uint32_t)zt, g.div_lz);
+    X[2] = zt - X[3] * g.L[2];
     X[0] = 2 * xh + ((p + X[1] + X[2] + X[3]) & 1);
-
-    hop_pair<S, 0, DAGGER>(acc, g, links, g.stride, in, r, p, cb, X);
-    hop_pair<S, 1, DAGGER>(acc, g, links, g.stride, in, r, p, cb, X);
-    hop_pair<S, 2, DAGGER>(acc, g, links, g.stride, in, r, p, cb, X);
-    hop_pair<S, 3, DAGGER>(acc, g, links, g.stride, in, r, p, cb, X);
-
-    if constexpr (XPAY) {
-      load_spinor<S>(xs, r, cb, x);
+    SpinorBuf<S> ib[NR];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc.v[s][c] = x.v[s][c] + a * acc.v[s][c];
-    }
-    store_spinor<S>(out, r, cb, acc);
+    for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0);
+    hop_pair<S, 0, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X);
+    hop_pair<S, 1, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X);
+    hop_pair<S, 2, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X);
+    hop_pair<S, 3, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X);
   }
-  if constexpr (DOT != DOT_NONE) {
-    const int nb = gridDim.x;
-    double* part = partials + ((int64_t)r * nb + blockIdx.x) * kMaxDot;
-    if constexpr (DOT == DOT_YO) {
-      double d[2] = {0.0, 0.0};
-      if (valid) {
-        Spinor<R> y;
-        load_spinor<S>(ys, r, cb, y);
-        R re = 0, im = 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (!on[k]) continue;  // uniform across the block
+    Spinor<R> x;
+    if (valid) {
+      if constexpr (XPAY) {
+        load_spinor<S>(xs, rhs[k], cb, x);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            cx<R> t = cmulc(y.v[s][c], acc.v[s][c]);
-            re += t.re;
-            im += t.im;
-          }
-        d[0] = re;
-        d[1] = im;
+          for (int c = 0; c < 3; ++c) acc[k].v[s][c] = x.v[s][c] + a * acc[k].v[s][c];
       }
-      block_sum_store<2>(d, part);
-    } else if constexpr (DOT == DOT_OX) {
-      double d[3] = {0.0, 0.0, 0.0};
-      if (valid) {
-        R re = 0, im = 0, nn = 0;
+      store_spinor<S>(out, rhs[k], cb, acc[k]);
+    }
+    if constexpr (DOT != DOT_NONE) {
+      const int nb = (g.slab ? 8 : 1) * g.site_blocks;
+      double* part = partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot;
+      if constexpr (DOT == DOT_YO) {
+        double d[2] = {0.0, 0.0};
+        if (valid) {
+          Spinor<R> y;
+          load_spinor<S>(ys, rhs[k], cb, y);
+          R re = 0, im = 0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+          for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            cx<R> t = cmulc(acc.v[s][c], x.v[s][c]);
-            re += t.re;
-            im += t.im;
-            nn += acc.v[s][c].re * acc.v[s][c].re + acc.v[s][c].im * acc.v[s][c].im;
-          }
-        d[0] = re;
-        d[1] = im;
-        d[2] = nn;
+            for (int c = 0; c < 3; ++c) {
+              const cx<R> t = cmulc(y.v[s][c], acc[k].v[s][c]);
+              re += t.re;
+              im += t.im;
+            }
+          d[0] = re;
+          d[1] = im;
+        }
+        block_sum_store<2>(d, part);
+      } else if constexpr (DOT == DOT_OX) {
+        double d[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+          R re = 0, im = 0, nn = 0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const cx<R> t = cmulc(acc[k].v[s][c], x.v[s][c]);
+              re += t.re;
+              im += t.im;
+              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
+            }
+          d[0] = re;
+          d[1] = im;
+          d[2] = nn;
+        }
+        block_sum_store<3>(d, part);
+      } else {
+        double d[1] = {0.0};
+        if (valid) {
+          R nn = 0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
+          d[0] = nn;
+        }
+        block_sum_store<1>(d, part);
       }
-      block_sum_store<3>(d, part);
-    } else {
-      double d[1] = {0.0};
-      if (valid) {
-        R nn = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            nn += acc.v[s][c].re * acc.v[s][c].re + acc.v[s][c].im * acc.v[s][c].im;
-        d[0] = nn;
-      }
-      block_sum_store<1>(d, part);
     }
   }
 }
 
-static GeomView view(const Geom& g) {
-  GeomView v;
-  for (int m = 0; m < 4; ++m) v.L[m] = g.L[m];
-  v.Lxh = g.Lxh;
-  v.Vh = g.Vh;
-  v.tap = g.tap;
-  v.stride = g.stride;
-  return v;
+// ---- launch configuration ---------------------------------------------------------
+static DslashGeom make_dgeom(const Geom& geo, int nrhs, const LaunchCfg& c) {
+  DslashGeom g;
+  for (int m = 0; m < 4; ++m) g.L[m] = geo.L[m];
+  g.Lxh = geo.Lxh;
+  g.Vh = geo.Vh;
+  g.tap = geo.tap;
+  g.stride = geo.stride;
+  g.div_lxh = make_fastdiv(geo.Lxh);
+  g.div_ly = make_fastdiv(geo.L[1]);
+  g.div_lz = make_fastdiv(geo.L[2]);
+  g.nrhs = nrhs;
+  g.ngroups = (nrhs + c.nr - 1) / c.nr;
+  g.slab = (geo.L[2] % 8 == 0) ? 1 : 0;
+  g.slab_t_sites = geo.Lxh * geo.L[1] * (geo.L[2] / 8);
+  g.div_slab_t = make_fastdiv(g.slab_t_sites > 0 ? g.slab_t_sites : 1);
+  if (g.slab) g.site_blocks = ((geo.Vh >> 3) + c.block - 1) / c.block;
+  else g.site_blocks = (geo.Vh + c.block - 1) / c.block;
+  return g;
+}
+
+static unsigned grid_blocks(const DslashGeom& g) {
+  if (g.slab) return 8u * (unsigned)(g.site_blocks * g.ngroups);
+  const unsigned per = (unsigned)((g.site_blocks * g.ngroups + 7) / 8);
+  return 8u * per;
 }
 
 static FieldView fview(const Field& f) { return FieldView{f.ptr, f.stride, f.nrhs}; }
 static FieldView fview(const Field* f) { return f ? fview(*f) : FieldView{nullptr, 0, 0}; }
 
-template <class S, bool DAGGER, bool XPAY>
-static void launch_dot(int dot, dim3 grid, hipStream_t s, const GeomView& g, const char* links,
-                       FieldView fo, FieldView fi, FieldView fx, FieldView fy, typename S::real a,
-                       int p, const int* active, double* partials) {
+template <class S, bool DAGGER, bool XPAY, int NR>
+static void launch_dot(int dot, unsigned grid, int block, hipStream_t s, const DslashGeom& g,
+                       const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
+                       typename S::real a, int p, const int* active, double* partials) {
   switch (dot) {
     case DOT_YO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_YO><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR><<<grid, block, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     case DOT_OX:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OX><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR><<<grid, block, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     case DOT_OO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OO><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR><<<grid, block, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     default:
-      dslash_kernel<S, DAGGER, XPAY, DOT_NONE><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR><<<grid, block, 0, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
   }
 }
 
-template <class S>
-static hipError_t launch_typed(const wd_gauge* gg, const DslashArgs& d, hipStream_t s) {
-  const GeomView g = view(gg->geom);
+template <class S, int NR>
+static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
+  const DslashGeom g = make_dgeom(gg->geom, d.out.nrhs, c);
   const char* links = static_cast<const char*>(gg->link[S::prec]);
-  dim3 grid((g.Vh + kBlock - 1) / kBlock, d.out.nrhs);
+  const unsigned grid = grid_blocks(g);
   FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
   using R = typename S::real;
   const R ar = static_cast<R>(d.a);
   const int dot = d.xpay ? d.dot : DOT_NONE;
   if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, true, false>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, true, true, NR>(dot, grid, c.block, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, true, false, NR>(DOT_NONE, grid, c.block, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   } else {
-    if (d.xpay) launch_dot<S, false, true>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, false, false>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, false, true, NR>(dot, grid, c.block, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, false, false, NR>(DOT_NONE, grid, c.block, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   }
-  return hipGetLastError();
+}
+
+template <class S>
+static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
+  switch (c.nr) {
+    case 2: launch_nr<S, 2>(gg, d, c, s); break;
+    case 3: launch_nr<S, 3>(gg, d, c, s); break;
+    case 4: launch_nr<S, 4>(gg, d, c, s); break;
+    default: launch_nr<S, 1>(gg, d, c, s); break;
+  }
+}
+
+void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
+                       hipStream_t s) {
+  switch (prec) {
+    case WD_FP64: launch_cfg<SF64>(g, d, c, s); break;
+    case WD_FP32: launch_cfg<SF32>(g, d, c, s); break;
+    case WD_HALF_I16: launch_cfg<SI16>(g, d, c, s); break;
+    default: launch_cfg<SF16>(g, d, c, s); break;
+  }
 }
 
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
-  switch (prec) {
-    case WD_FP64: return launch_typed<SF64>(g, d, s);
-    case WD_FP32: return launch_typed<SF32>(g, d, s);
-    case WD_HALF_I16: return launch_typed<SI16>(g, d, s);
-    case WD_HALF_F16: return launch_typed<SF16>(g, d, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (prec < WD_FP64 || prec > WD_HALF_F16) return hipErrorInvalidValue;
+  const LaunchCfg c = tuned_dslash_config(g, prec, d, s);
+  launch_dslash_cfg(g, prec, d, c, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int out_parity,
@@ -286,6 +548,9 @@ hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, i
   return launch_dslash_ex(g, prec, d, s);
 }
 
-int dslash_blocks(const Geom& g) { return (g.Vh + kBlock - 1) / kBlock; }
+int dslash_partial_blocks(const Geom& geo, int nrhs, const LaunchCfg& c) {
+  const DslashGeom g = make_dgeom(geo, nrhs, c);
+  return (g.slab ? 8 : 1) * g.site_blocks;
+}
 
 }  // namespace wd

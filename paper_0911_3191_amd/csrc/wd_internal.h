@@ -72,7 +72,24 @@ struct DslashArgs {
   const int* active = nullptr;
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
-int dslash_blocks(const Geom& g);
+
+// Launch shape of the dslash: right-hand sides per thread and threads per
+// workgroup.  The workgroup size is fixed at 256 so that fused dot products
+// reduce in the same order whatever the batch; only nr is tuned.
+struct LaunchCfg {
+  int nr;
+  int block;
+};
+void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
+                       hipStream_t s);
+// Partial records per RHS written by a dslash launch with a fused dot.
+int dslash_partial_blocks(const Geom& geo, int nrhs, const LaunchCfg& c);
+// Autotuner (wd_tune.cpp): the configuration to use for this launch; times
+// the candidates on first use of (lattice, precision, nrhs) unless the
+// stream is being captured.
+LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
+// Runs the tuner for (prec, nrhs) on the given fields (out = D in is computed).
+void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, hipStream_t s);
 
 // out_p = D_{p,1-p} in (dagger: adjoint).  When xpay_src is non-null:
 // out = xpay_src + a * D in (xpay_src has parity p, same precision).

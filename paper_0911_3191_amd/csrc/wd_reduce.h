@@ -28,9 +28,16 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double* out) {
 #pragma unroll
     for (int k = 0; k < N; ++k) sm[k][wid] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
+    const int nw = (int)blockDim.x >> 6;  // 1, 2 or 4 waves
 #pragma unroll
-    for (int k = 0; k < N; ++k) out[k] = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+    for (int k = 0; k < N; ++k) {
+      double t = sm[k][0];
+      if (nw == 2) t += sm[k][1];
+      if (nw == 4) t = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+      out[k] = t;
+    }
+  }
 }
 
 // Fixed-order sum of nb partial records (stride kMaxDot) into res[0..N).

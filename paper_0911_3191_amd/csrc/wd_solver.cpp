@@ -45,7 +45,7 @@ static Layout layout(const Geom& g, int kind, wd_prec inner, int nrhs) {
   // low precision: BiCGstab r^, r~, p, v, t, x^; CG r^, p, q, w, x^; plus an odd temporary
   L.n_lo_even = (kind == WD_SOLVER_CG) ? 5 : 6;
   L.n_lo_odd = 1;
-  const int nb = (g.Vh + 255) / 256;
+  const int nb = std::max((g.Vh + 255) / 256, dslash_partial_blocks(g, nrhs, LaunchCfg{1, 256}));
   L.partials = align256(sizeof(double) * kMaxDotHost * nb * (size_t)nrhs);
   L.scalars = align256(sizeof(double) * SC_COUNT * (size_t)nrhs);
   L.flags = align256(sizeof(int) * FL_COUNT * (size_t)nrhs);
@@ -66,7 +66,7 @@ struct wd_solver {
   hipStream_t s;
   double* x_out;
   const double* b_in;
-  int nrhs, nb;
+  int nrhs, nb, nb_dslash;  // partial records per RHS: BLAS-1 kernels, fused-dot dslash
   wd::Field bhat, x, r, rn, to64;
   wd::Field rh, rt, p, v, t, xh, to;  // CG uses v as q and t as w; rt unused
   double* partials;
@@ -115,8 +115,10 @@ static hipError_t mhat_into(wd_solver* h, wd_prec prec, const Field& out, const 
 }
 
 static hipError_t fin(wd_solver* h, int stage, const int* mask) {
-  return solver_finalize(stage, h->nrhs, h->nb, h->partials, h->sc, h->fl, h->active, h->rumask,
-                         mask, h->prm.delta, h->prm.tol, h->s);
+  // the stages that follow a dslash with a fused dot read the dslash's partial records
+  const bool after_dslash = stage == FIN_BICG_ALPHA || stage == FIN_BICG_OMEGA || stage == FIN_CG_ALPHA;
+  return solver_finalize(stage, h->nrhs, after_dslash ? h->nb_dslash : h->nb, h->partials, h->sc,
+                         h->fl, h->active, h->rumask, mask, h->prm.delta, h->prm.tol, h->s);
 }
 
 #define WD_TRY(expr)                         \
@@ -309,6 +311,7 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   h->b_in = b;
   h->nrhs = prm->nrhs;
   h->nb = (h->geom.Vh + 255) / 256;
+  h->nb_dslash = dslash_partial_blocks(h->geom, h->nrhs, LaunchCfg{1, 256});
   const Layout L = layout(h->geom, solver, prm->inner, prm->nrhs);
   char* p = static_cast<char*>(workspace);
   auto take_hi = [&]() { Field f{p, h->geom.stride, h->nrhs}; p += L.hi_field; return f; };
@@ -348,7 +351,10 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
     delete h;
     return hip_fail(e, "pinned host buffer");
   }
-  e = prepare(h);
+  e = prepare(h);  // its FP64 dslash launches pick their own launch shape
+  // pick the inner-precision launch shape before any graph capture, on
+  // (p -> odd temporary); the temporary is scratch at this point
+  if (e == hipSuccess) tune_dslash(g, prm->inner, h->to, h->p, h->s);
   if (e == hipSuccess) e = read_flags(h);
   if (e != hipSuccess) {
     (void)hipHostFree(h->h_fl);

@@ -1,0 +1,154 @@
+// Autotuner for the dslash launch shape (right-hand sides per thread).
+//
+// The first eager launch for a (lattice, precision, nrhs) times each
+// candidate with HIP events on the caller's stream, using the plain
+// out = D in form on the caller's own fields, and keeps the fastest.
+// Launches made while the stream is being captured into a graph, or whose
+// output aliases their xpay source, use the default shape instead and do not
+// tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
+// across processes (one "Lx Ly Lz Lt prec nrhs nr block" line per entry).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <algorithm>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int>;  // dims, prec, nrhs
+
+std::mutex g_mu;
+std::map<Key, LaunchCfg> g_cache;
+bool g_loaded = false;
+
+Key key_of(const wd_gauge* g, wd_prec prec, int nrhs) {
+  const Geom& geo = g->geom;
+  return Key{geo.L[0], geo.L[1], geo.L[2], geo.L[3] * 8 + static_cast<int>(prec), nrhs, 0};
+}
+
+LaunchCfg default_cfg(wd_prec prec, int nrhs) {
+  int nr = 1;
+  if (nrhs > 1) nr = (prec == WD_FP64) ? 1 : 2;
+  return LaunchCfg{nr, 256};
+}
+
+const char* cache_path() {
+  const char* p = std::getenv("WD_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void load_cache_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int lx, ly, lz, lt, prec, nrhs, nr, block;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &nr, &block) == 8) {
+    if (nr >= 1 && nr <= 4 && block == 256)
+      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, 0}] = LaunchCfg{nr, block};
+  }
+  std::fclose(f);
+}
+
+void save_entry_locked(const Key& k, const LaunchCfg& c) {
+  const char* path = cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), c.nr, c.block);
+  std::fclose(f);
+}
+
+bool tuning_enabled() {
+  const char* e = std::getenv("WD_TUNE");
+  return !(e && e[0] == '0');
+}
+
+// Milliseconds per launch of configuration c (plain out = D in), or -1.
+float time_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& plain, const LaunchCfg& c,
+               hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0f;
+  }
+  launch_dslash_cfg(g, prec, plain, c, s);  // warm-up
+  const int reps = 3;
+  (void)hipEventRecord(e0, s);
+  for (int i = 0; i < reps; ++i) launch_dslash_cfg(g, prec, plain, c, s);
+  (void)hipEventRecord(e1, s);
+  float ms = -1.0f;
+  if (hipGetLastError() == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+      hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+    ms /= reps;
+  else
+    ms = -1.0f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
+  DslashArgs plain = d;
+  plain.xpay = nullptr;
+  plain.dot = DOT_NONE;
+  plain.y = nullptr;
+  LaunchCfg best = default_cfg(prec, d.out.nrhs);
+  float best_ms = -1.0f;
+  // nr = 2 is also tried for a single RHS (its second slot stays empty): the
+  // per-slot branch changes how the compiler schedules the gathers.
+  for (int nr = 1; nr <= 4; ++nr) {
+    if (nr > std::max(d.out.nrhs, 2)) break;
+    const LaunchCfg c{nr, 256};
+    const float ms = time_cfg(g, prec, plain, c, s);
+    if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
+  const int nrhs = d.out.nrhs;
+  const Key k = key_of(g, prec, nrhs);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_cache_locked();
+    auto it = g_cache.find(k);
+    if (it != g_cache.end()) return it->second;
+  }
+  if (!tuning_enabled()) return default_cfg(prec, nrhs);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return default_cfg(prec, nrhs);
+  if (d.xpay && d.xpay->ptr == d.out.ptr) return default_cfg(prec, nrhs);
+  const LaunchCfg best = run_tuner(g, prec, d, s);
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_cache[k] = best;
+  save_entry_locked(k, best);
+  return best;
+}
+
+void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, hipStream_t s) {
+  DslashArgs d;
+  d.out = out;
+  d.in = in;
+  d.out_parity = 1;
+  (void)tuned_dslash_config(g, prec, d, s);
+}
+
+}  // namespace wd
