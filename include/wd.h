@@ -228,6 +228,49 @@ wd_status wd_solver_end(wd_solver *h, wd_solve_info *info);
  * and |b|^2 into out[nrhs][3] (host memory).  Synchronises the solver's stream. */
 wd_status wd_solver_residuals(wd_solver *h, double *out);
 
+/* ---- serving: continuous batching of independent solves ------------------------- */
+
+typedef struct wd_server wd_server;
+
+typedef struct {
+  int32_t max_slots;      /* solves in flight at once (one HIP stream each), 1..64 */
+  int32_t iters_per_pump; /* iterations each in-flight solve advances per wd_server_pump, >= 1 */
+} wd_serve_params;
+
+/* A scheduler over a caller-owned device arena (>= 256-byte aligned).  Each
+ * admitted request gets its solver workspace (wd_solve_workspace_bytes) from
+ * the arena and its own stream; requests wait in FIFO order until a slot and
+ * enough arena memory are free (admission by HBM footprint).  Gauge handles
+ * are shared read-only by the requests that use them. */
+wd_status wd_server_create(void *arena, size_t arena_bytes, const wd_serve_params *params,
+                           wd_server **out);
+
+/* Queue a solve (solver = WD_SOLVER_BICGSTAB or WD_SOLVER_CG) of
+ * (1 - kappa D) x = b with the given parameters (with use_graph, each solve
+ * replays its own captured iteration on its slot's stream).  x and
+ * b (device, full-lattice FP64, params->nrhs RHS) must stay valid until the
+ * request is reported done; b must already hold its values (the slot streams
+ * are non-blocking and do not wait on the caller's streams).  Returns
+ * WD_ENOMEM if the request's workspace can never fit the arena.  Never
+ * blocks. */
+wd_status wd_server_submit(wd_server *s, int32_t solver, const wd_gauge *g, double kappa, double *x,
+                           const double *b, const wd_solve_params *params, int64_t *request_id);
+
+/* One scheduling round: admit queued requests that fit, launch one round of
+ * iterations on every in-flight solve (each on its own stream, so they
+ * overlap on the device), then complete them; finished solves release their
+ * slot and memory.  Reports the in-flight and queued counts. */
+wd_status wd_server_pump(wd_server *s, int32_t *n_active, int32_t *n_queued);
+
+/* Result of a request: *done = 1 once finished (info[0..nrhs) filled, status
+ * = the solve's wd_status, e.g. WD_EINVAL for a NaN source), 0 while queued
+ * or in flight.  Calls on one server must not overlap (one host thread). */
+wd_status wd_server_poll(wd_server *s, int64_t request_id, int32_t *done, int32_t *status,
+                         wd_solve_info *info);
+
+/* Destroys the scheduler (requests still in flight are finished first). */
+wd_status wd_server_destroy(wd_server *s);
+
 #ifdef __cplusplus
 }
 #endif

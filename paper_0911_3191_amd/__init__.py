@@ -9,8 +9,9 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (PREC, WD_EBREAKDOWN, WD_FP32, WD_FP64, WD_HALF_F16, WD_HALF_I16, WD_NOT_CONVERGED, WD_OK,
-                   Lattice, WDError, check, lib, ptr, stream_ptr)
+from ._lib import (PREC, WD_EBREAKDOWN, WD_EDEVICE, WD_EINVAL, WD_ENOMEM, WD_EUNSUPPORTED, WD_FP32, WD_FP64,
+                   WD_HALF_F16, WD_HALF_I16, WD_NOT_CONVERGED, WD_OK, Lattice, WDError, check, lib, ptr,
+                   stream_ptr)
 
 __all__ = [
     "Lattice", "WDError", "Gauge", "PREC", "WD_FP64", "WD_FP32", "WD_HALF_I16", "WD_HALF_F16",

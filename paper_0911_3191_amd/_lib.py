@@ -80,11 +80,10 @@ def lib():
 
 
 def _declare_solver(L):
-    """Solver entry points (present once the solver translation unit is built)."""
-    if not hasattr(L, "wd_solve_workspace_bytes"):
-        return
-    from ._solver_types import declare
+    """Solver and serving entry points."""
+    from ._solver_types import declare, declare_server
     declare(L)
+    declare_server(L)
 
 
 def check(status: int, where: str) -> int:

@@ -39,3 +39,21 @@ def declare(L) -> None:
     L.wd_solver_end.restype = i32
     L.wd_solver_residuals.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.wd_solver_residuals.restype = i32
+
+
+class ServeParams(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("iters_per_pump", ctypes.c_int32)]
+
+
+def declare_server(L) -> None:
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    L.wd_server_create.argtypes = [vp, sz, ctypes.POINTER(ServeParams), ctypes.POINTER(vp)]
+    L.wd_server_create.restype = i32
+    L.wd_server_submit.argtypes = [vp, i32, vp, dbl, vp, vp, ctypes.POINTER(SolveParams), ctypes.POINTER(i64)]
+    L.wd_server_submit.restype = i32
+    L.wd_server_pump.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.wd_server_pump.restype = i32
+    L.wd_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(SolveInfo)]
+    L.wd_server_poll.restype = i32
+    L.wd_server_destroy.argtypes = [vp]
+    L.wd_server_destroy.restype = i32

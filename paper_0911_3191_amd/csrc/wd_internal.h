@@ -79,6 +79,11 @@ hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d
 struct LaunchCfg {
   int nr;
   int block;
+  int gslow = 0;    // RHS group slowest in an XCD's sweep (else fastest)
+  int nsub = 1;     // y-sub-slabs an XCD sweeps one after the other
+  int link_nt = 0;  // link loads marked streaming
+  int out_nt = 0;   // output stores marked streaming
+  int wgs = 0;      // cap on workgroups per CU (0: registers decide)
 };
 void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
                        hipStream_t s);
@@ -159,6 +164,11 @@ hipError_t solver_finalize(int stage, int nrhs, int nb, const double* partials, 
 hipError_t solver_cg_tighten(int nrhs, double* sc, const int* fl, const int* mask, double tol,
                              hipStream_t s);
 hipError_t solver_init_flags(int nrhs, int* fl, int* active, int* rumask, hipStream_t s);
+
+// ---- two-phase stepping (wd_solver.cpp), used by the serving scheduler ---------------
+bool solver_finished(wd_solver* h);
+hipError_t solver_issue(wd_solver* h);   // launch one iteration, returns at once
+wd_status solver_complete(wd_solver* h); // wait for it, reliable update if triggered
 
 // ---- error reporting ------------------------------------------------------------
 void set_error(const std::string& msg);

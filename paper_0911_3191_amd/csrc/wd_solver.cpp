@@ -378,35 +378,49 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   return WD_OK;
 }
 
-wd_status wd_solver_step(wd_solver* h, int32_t n_iters, int32_t* done) {
-  set_error("");
-  if (!h) return fail(WD_EINVAL, "solver handle is NULL");
-  if (n_iters < 1) return fail(WD_EINVAL, "n_iters must be >= 1");
-  for (int it = 0; it < n_iters && !h->finished; ++it) {
-    bool any = false;
-    for (int k = 0; k < h->nrhs; ++k) any |= !h->done_rhs[k];
-    if (!any || h->loops >= h->prm.maxiter) {
-      h->finished = true;
-      break;
-    }
-    hipError_t e = hipSuccess;
-    if (h->prm.use_graph && h->s) {
-      if (!h->graph_ready) {
-        e = hipStreamBeginCapture(h->s, hipStreamCaptureModeRelaxed);
-        if (e == hipSuccess) {
-          hipError_t eb = iteration_body(h);
-          e = hipStreamEndCapture(h->s, &h->graph);
-          if (eb != hipSuccess) e = eb;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
-        if (e == hipSuccess) h->graph_ready = true;
+}  // extern "C"
+
+namespace wd {
+
+bool solver_finished(wd_solver* h) {
+  if (h->finished) return true;
+  bool any = false;
+  for (int k = 0; k < h->nrhs; ++k) any |= !h->done_rhs[k];
+  if (!any || h->loops >= h->prm.maxiter) h->finished = true;
+  return h->finished;
+}
+
+// Launch one iteration and the asynchronous copy of its flags; returns at once.
+hipError_t solver_issue(wd_solver* h) {
+  hipError_t e = hipSuccess;
+  if (h->prm.use_graph && h->s) {
+    if (!h->graph_ready) {
+      e = hipStreamBeginCapture(h->s, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        hipError_t eb = iteration_body(h);
+        e = hipStreamEndCapture(h->s, &h->graph);
+        if (eb != hipSuccess) e = eb;
       }
-      if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->s);
-    } else {
-      e = iteration_body(h);
+      if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) h->graph_ready = true;
     }
-    if (e == hipSuccess) e = read_flags(h);
-    if (e != hipSuccess) return hip_fail(e, "solver iteration");
+    if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->s);
+  } else {
+    e = iteration_body(h);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->h_fl, h->fl, sizeof(int) * FL_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->h_sc, h->sc, sizeof(double) * SC_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s);
+  return e;
+}
+
+// Wait for the issued iteration, account for it, run the reliable update if
+// one was triggered and (CG) the search-direction update.
+wd_status solver_complete(wd_solver* h) {
+  hipError_t e = hipStreamSynchronize(h->s);
+  if (e != hipSuccess) return hip_fail(e, "solver iteration");
+  {
     ++h->loops;
     bool any_ru = false;
     for (int k = 0; k < h->nrhs; ++k) {
@@ -445,10 +459,25 @@ wd_status wd_solver_step(wd_solver* h, int32_t n_iters, int32_t* done) {
       if (e != hipSuccess) return hip_fail(e, "cg p update");
     }
   }
-  bool any = false;
-  for (int k = 0; k < h->nrhs; ++k) any |= !h->done_rhs[k];
-  if (!any || h->loops >= h->prm.maxiter) h->finished = true;
-  if (done) *done = h->finished ? 1 : 0;
+  solver_finished(h);
+  return WD_OK;
+}
+
+}  // namespace wd
+
+extern "C" {
+
+wd_status wd_solver_step(wd_solver* h, int32_t n_iters, int32_t* done) {
+  set_error("");
+  if (!h) return fail(WD_EINVAL, "solver handle is NULL");
+  if (n_iters < 1) return fail(WD_EINVAL, "n_iters must be >= 1");
+  for (int it = 0; it < n_iters && !solver_finished(h); ++it) {
+    hipError_t e = solver_issue(h);
+    if (e != hipSuccess) return hip_fail(e, "solver iteration");
+    wd_status st = solver_complete(h);
+    if (st) return st;
+  }
+  if (done) *done = solver_finished(h) ? 1 : 0;
   return WD_OK;
 }
 
