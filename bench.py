@@ -34,6 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA rate without packed-FP32 instructions (which this build does
+# not use): 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 DIMS = (48, 48, 48, 96)
 KAPPA = 0.124
 EPS, SEED = 0.3, 5
@@ -78,6 +81,33 @@ def prepare_bytes(nrhs: int) -> int:
             + nrhs * 2 * s64 + dslash_bytes("fp64", nrhs, 1) + nrhs * 4 * s64)
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("wd_dslash.hip", "wd_device.h", "wd_reduce.h"):
+        with open(os.path.join(ROOT, "paper_0911_3191_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str, dims) -> dict | None:
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (same hash); otherwise None."""
+    path = os.path.join(ROOT, "profiles", "dslash_traffic_48x48x48x96.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("| ") and kernel in line:
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                rec = {"fetch_bytes": float(cells[1]), "write_bytes": float(cells[2]),
+                       "source_hash": cells[3]}
+    if not rec or rec["source_hash"] != kernel_source_hash():
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +120,8 @@ def parse():
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--cpu-sample-sites", type=int, default=200000,
                     help="output sites of the oracle dslash timed for the CPU baseline")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the Poisson serving run (0: skip it)")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter scaling)")
     return ap.parse_args()
@@ -171,11 +203,14 @@ def main():
     fp64 = None
     if not args.no_fp64_reference:
         p64 = wd.solve_params(tol=1e-12, maxiter=20000, inner="fp64", delta=0.0, nrhs=1, use_graph=True)
-        del ws
+        ws = None
         torch.cuda.empty_cache()
         ws64 = wd.new_workspace(lat, p64, "bicgstab")
         b0 = b[0:1].contiguous()
         x0 = torch.zeros_like(b0)
+        with torch.cuda.stream(stream):  # untimed: tunes the single-RHS FP64 launch shape
+            wd.bicgstab_solve(gauge, KAPPA, x0, b0, p64, ws64, stream)
+        x0.zero_()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         with torch.cuda.stream(stream):
@@ -189,10 +224,15 @@ def main():
         torch.cuda.empty_cache()
 
     # ---- dominant kernel: 12-RHS dslash in the inner precision, HIP events on its stream ----
+    # input: 12 complex Gaussian fields (torch's device generator, seed 11)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    gsrc = torch.randn((NRHS, V, 4, 3, 2), dtype=torch.float64, device=dev, generator=gen)
+    torch.cuda.synchronize()
     fin = wd.new_field(lat, inner, NRHS)
     fout = wd.new_field(lat, inner, NRHS)
     with torch.cuda.stream(stream):
-        wd.wd_spinor_encode_full(lat, inner, NRHS, 1, fin, b, stream)
+        wd.wd_spinor_encode_full(lat, inner, NRHS, 1, fin, gsrc, stream)
         for _ in range(3):
             wd.wilson_dslash(gauge, fout, fin, 0, 0, inner, NRHS, stream)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -204,6 +244,9 @@ def main():
     t_dslash = ev0.elapsed_time(ev1) / args.dslash_reps * 1e-3
     dbytes = dslash_bytes(inner, NRHS) * Vh
     achieved = dbytes / t_dslash / 1e9
+    dflops = 1320 * Vh * NRHS
+    tflops = dflops / t_dslash / 1e12
+    traffic = profiled_traffic(f"dslash_{inner}_{NRHS}rhs", dims)
     del fin, fout
 
     # single-RHS dslash in every precision (context for the roofline)
@@ -212,7 +255,7 @@ def main():
         fi = wd.new_field(lat, prec, 1)
         fo = wd.new_field(lat, prec, 1)
         with torch.cuda.stream(stream):
-            wd.wd_spinor_encode_full(lat, prec, 1, 1, fi, b[0:1], stream)
+            wd.wd_spinor_encode_full(lat, prec, 1, 1, fi, gsrc[0:1], stream)
             for _ in range(3):
                 wd.wilson_dslash(gauge, fo, fi, 0, 0, prec, 1, stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -227,16 +270,46 @@ def main():
                        "gflops": round(1320 * Vh / t / 1e9, 1)}
         del fi, fo
     log(f"dslash table {table}")
+    del gsrc
+    torch.cuda.empty_cache()
 
-    if args.copy_probe_gb > 0:
-        n = int(args.copy_probe_gb * 1e9) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
+    # practical bandwidth of a plain device copy (read + write), HIP events
+    ncopy = int(max(args.copy_probe_gb, 4.0) * 1e9) // 8
+    src = torch.ones(ncopy, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(5):
             dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: {n * 8 / 1e9:.2f} GB read + written, 3 launches")
-        del src, dst
+        c1.record(stream)
+    c1.synchronize()
+    copy_gbs = 2 * ncopy * 8 / (c0.elapsed_time(c1) / 5 * 1e-3) / 1e9
+    log(f"copy: {ncopy * 8 / 1e9:.2f} GB read + written at {copy_gbs:.0f} GB/s")
+    del src, dst
+
+    # ---- serving: Poisson arrivals over 8 resident fields of three lattice sizes ----
+    serve = None
+    if args.serve_requests > 0:
+        from paper_0911_3191_amd.serve import make_fields, serve_stream
+        b = x = ws = None
+        torch.cuda.empty_cache()
+        t3 = time.time()
+        fields = make_fields(inner=inner)
+        log(f"serving fields built in {time.time() - t3:.1f}s")
+        serve = serve_stream(fields, n_requests=args.serve_requests, rate=20.0, seed=7, max_slots=16,
+                             inner=inner, log=log)
+        # the same stream with the arena cut to about twice the largest footprint,
+        # so that admission by HBM footprint binds
+        tight = 2 * max(serve["footprint_bytes"].values()) + 4096
+        serve_tight = serve_stream(fields, n_requests=max(args.serve_requests // 3, 20), rate=20.0, seed=8,
+                                   arena_bytes=tight, max_slots=16, inner=inner, log=log)
+        serve["budget_2x_largest"] = {k: serve_tight[k] for k in
+                                      ("requests", "arena_bytes", "p50_ms", "p99_ms", "solves_per_s",
+                                       "max_in_flight", "max_queued")}
+        del fields
+        torch.cuda.empty_cache()
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
     cpu = None
@@ -279,10 +352,13 @@ def main():
                    "lattice": args.dims, "kappa": KAPPA, "eps": EPS, "seed": SEED, "nrhs": NRHS,
                    "sources": "12 spin-colour point sources at the origin", "inner": inner,
                    "delta": 0.1, "recon": 12, "graph": True, "arith": "f32 inner, f64 reductions/updates"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"dslash_kernel<{inner}> 12-RHS", "bytes_per_launch": dbytes,
-                     "us_per_launch": round(t_dslash * 1e6, 1)},
+        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic,
+                     "kernel": f"dslash_kernel<{inner}> {NRHS}-RHS",
+                     "flops_per_launch": dflops, "bytes_per_launch": dbytes,
+                     "us_per_launch": round(t_dslash * 1e6, 1),
+                     "hbm_achieved_GBps": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
         "time_to_solution": {"mixed_batch_s": round(ms_per_step * 1e-3, 3),
                              "mixed_per_rhs_s": round(per_rhs_mixed, 4),
                              "fp64_single_rhs_s": round(fp64["seconds"], 3) if fp64 else None,
@@ -292,6 +368,8 @@ def main():
                              "true_rel_resid_max": worst_res,
                              "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None},
         "dslash_single_rhs": table,
+        "copy_GBps": round(copy_gbs, 1),
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -24,7 +24,13 @@ wd_status fail(wd_status code, const std::string& msg) {
 
 // Chunk arrays are padded to a multiple of 64 sites (one wavefront) so that
 // every chunk array starts 1 KiB-aligned relative to the field base.
-int64_t field_stride(int64_t Vh) { return (Vh + 63) / 64 * 64; }
+int64_t field_stride(int64_t Vh) {
+  static const int64_t pad = [] {
+    const char* e = std::getenv("WD_STRIDE_PAD");
+    return e ? std::max<int64_t>(0, std::atoll(e)) : int64_t(0);
+  }();
+  return (Vh + 63) / 64 * 64 + pad;
+}
 
 Geom make_geom(const wd_lattice& lat) {
   Geom g;

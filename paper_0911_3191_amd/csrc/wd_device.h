@@ -158,22 +158,32 @@ __device__ __forceinline__ void load_spinor_raw(const FieldView& f, int r, int64
   }
 }
 
+// 16-byte store; NT marks it streaming (not kept in L2).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef uint32_t uvec4 __attribute__((ext_vector_type(4)));
+template <bool NT, typename V>
+__device__ __forceinline__ void st16(V* p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Encode 24 reals of the arithmetic type into one site of the field.
-template <class S>
+template <class S, bool NT = false>
 __device__ __forceinline__ void store_spinor(const FieldView& f, int r, int64_t i,
                                              const Spinor<typename S::real>& s) {
   if constexpr (S::prec == WD_FP64) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       cx<double> z = s.v[k / 3][k % 3];
-      reinterpret_cast<double2*>(const_cast<char*>(chunk_base<S>(f, r, k)))[i] = make_double2(z.re, z.im);
+      st16<NT>(reinterpret_cast<dvec2*>(const_cast<char*>(chunk_base<S>(f, r, k))) + i, dvec2{z.re, z.im});
     }
   } else if constexpr (S::prec == WD_FP32) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       cx<float> a = s.v[(2 * k) / 3][(2 * k) % 3], b = s.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
-      reinterpret_cast<float4*>(const_cast<char*>(chunk_base<S>(f, r, k)))[i] =
-          make_float4(a.re, a.im, b.re, b.im);
+      st16<NT>(reinterpret_cast<fvec4*>(const_cast<char*>(chunk_base<S>(f, r, k))) + i,
+               fvec4{a.re, a.im, b.re, b.im});
     }
   } else {
     float nm = 0.0f;
@@ -208,8 +218,8 @@ __device__ __forceinline__ void store_spinor(const FieldView& f, int r, int64_t 
         }
         w[j] = (uint32_t)lo | ((uint32_t)hi << 16);
       }
-      reinterpret_cast<uint4*>(const_cast<char*>(chunk_base<S>(f, r, k)))[i] =
-          make_uint4(w[0], w[1], w[2], w[3]);
+      st16<NT>(reinterpret_cast<uvec4*>(const_cast<char*>(chunk_base<S>(f, r, k))) + i,
+               uvec4{w[0], w[1], w[2], w[3]});
     }
   }
 }

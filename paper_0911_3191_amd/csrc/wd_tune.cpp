@@ -1,4 +1,6 @@
-// Autotuner for the dslash launch shape (right-hand sides per thread).
+// Autotuner for the dslash launch shape: right-hand sides per thread (nr),
+// RHS-group order in an XCD's sweep (gslow) and the cache policy of the link
+// loads (link_nt).
 //
 // The first eager launch for a (lattice, precision, nrhs) times each
 // candidate with HIP events on the caller's stream, using the plain
@@ -6,7 +8,10 @@
 // Launches made while the stream is being captured into a graph, or whose
 // output aliases their xpay source, use the default shape instead and do not
 // tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
-// across processes (one "Lx Ly Lz Lt prec nrhs nr block" line per entry).
+// across processes (one "Lx Ly Lz Lt prec nrhs nr block gslow nsub link_nt"
+// line per entry); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
+// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt]" forces a shape (y-sub-slabs,
+// nsub, are not searched: they did not pay on the lattices measured).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -51,10 +56,12 @@ void load_cache_locked() {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  int lx, ly, lz, lt, prec, nrhs, nr, block;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &nr, &block) == 8) {
-    if (nr >= 1 && nr <= 4 && block == 256)
-      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, 0}] = LaunchCfg{nr, block};
+  int lx, ly, lz, lt, prec, nrhs, nr, block, gslow, nsub, nt;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &nr, &block,
+                     &gslow, &nsub, &nt) == 11) {
+    if (nr >= 1 && nr <= 4 && block == 256 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
+        (nt == 0 || nt == 1))
+      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, 0}] = LaunchCfg{nr, block, gslow, nsub, nt};
   }
   std::fclose(f);
 }
@@ -64,14 +71,20 @@ void save_entry_locked(const Key& k, const LaunchCfg& c) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-               std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), c.nr, c.block);
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), c.nr, c.block, c.gslow, c.nsub,
+               c.link_nt);
   std::fclose(f);
 }
 
 bool tuning_enabled() {
   const char* e = std::getenv("WD_TUNE");
   return !(e && e[0] == '0');
+}
+
+bool verbose() {
+  const char* e = std::getenv("WD_TUNE_VERBOSE");
+  return e && e[0] == '1';
 }
 
 // Milliseconds per launch of configuration c (plain out = D in), or -1.
@@ -110,11 +123,23 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
   // per-slot branch changes how the compiler schedules the gathers.
   for (int nr = 1; nr <= 4; ++nr) {
     if (nr > std::max(d.out.nrhs, 2)) break;
-    const LaunchCfg c{nr, 256};
-    const float ms = time_cfg(g, prec, plain, c, s);
-    if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
-      best_ms = ms;
-      best = c;
+    const int groups = (d.out.nrhs + nr - 1) / nr;
+    for (int gslow = 0; gslow <= (groups > 1 ? 1 : 0); ++gslow) {
+      for (int nt = 0; nt <= 1; ++nt) {
+        const LaunchCfg c{nr, 256, gslow, 1, nt};
+        // the better of two timings, so a clock ramp-up does not decide
+        float ms = time_cfg(g, prec, plain, c, s);
+        const float ms2 = time_cfg(g, prec, plain, c, s);
+        if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
+        if (verbose())
+          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: nr %d gslow %d link_nt %d -> %.1f us\n",
+                       g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs,
+                       nr, gslow, nt, ms * 1e3f);
+        if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+          best_ms = ms;
+          best = c;
+        }
+      }
     }
   }
   return best;
@@ -124,6 +149,14 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
 
 LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
   const int nrhs = d.out.nrhs;
+  // WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt]" forces one shape (tests sweep them with it)
+  if (const char* f = std::getenv("WD_DSLASH_SHAPE")) {
+    int nr = 1, gslow = 0, nsub = 1, nt = 0, ont = 0, wgs = 0;
+    const int n = std::sscanf(f, "%d,%d,%d,%d,%d,%d", &nr, &gslow, &nsub, &nt, &ont, &wgs);
+    if (n >= 3 && nr >= 1 && nr <= 4 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
+        (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8)
+      return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs};
+  }
   const Key k = key_of(g, prec, nrhs);
   {
     std::lock_guard<std::mutex> lock(g_mu);
