@@ -20,11 +20,17 @@ numpy arrays.  What each function follows in the paper:
       BiCGstab on M_hat and CG on the normal equations (Section 5.1)
   encode_spinor16, decode_spinor16, encode_link16, decode_link16
       16-bit storage with a per-site norm (Section 4.6)
+  encode_link8, decode_link8
+      the 8-real SU(3) parametrization (Appendix A.2)
+  gauge_fix_temporal, gauge_rotate_spinor
+      the temporal gauge of Section 4.3 (all temporal links the unit matrix
+      but on the last time slice) and the matching spinor rotation
 
 Pins (tests marked "not gpu"): a dense brute-force matrix built from the
 printed projector tables, the Clifford algebra, gamma5-hermiticity, the
 free-field plane-wave spectrum, gauge covariance, locality, dense solves,
-numpy's binary16 rounding.
+numpy's binary16 rounding, SU(3) unitarity and determinant of rebuilt
+links, gauge covariance of D under the temporal-gauge rotation.
 
 Layouts: gauge ``[V,4,3,3,2]``, full spinor ``[V,4,3,2]``, parity spinor
 ``[Vh,4,3,2]`` (any shape with those sizes, float64, C order).
@@ -86,6 +92,10 @@ def _load():
         lib.wdo_decode_spinor16.argtypes = [I, L, u16p, fp, dp]
         lib.wdo_encode_link16.argtypes = [I, L, dp, u16p]
         lib.wdo_decode_link16.argtypes = [I, L, u16p, dp]
+        lib.wdo_encode_link8.argtypes = [L, dp, dp]
+        lib.wdo_decode_link8.argtypes = [L, dp, dp]
+        lib.wdo_gauge_fix_temporal.argtypes = [ip, dp, dp, dp]
+        lib.wdo_gauge_rotate_spinor.argtypes = [ip, dp, dp, dp, I, I]
         _lib = lib
     return _lib
 
@@ -292,4 +302,45 @@ def decode_link16(kind: str, q):
     q = np.ascontiguousarray(q, dtype=np.uint16)
     out, op = _out(q.shape)
     _load().wdo_decode_link16(KIND[kind], q.size, q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), op)
+    return out
+
+
+def encode_link8(U):
+    """links [..., 3, 3, 2] -> [..., 8]: Re/Im a2, a3, b1, arg a1, arg c1 (Appendix A.2)."""
+    U, up = _in(U)
+    n = U.size // 18
+    out = np.zeros(U.shape[:-3] + (8,))
+    _load().wdo_encode_link8(n, up, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def decode_link8(p):
+    """[..., 8] -> links [..., 3, 3, 2] rebuilt as in Appendix A.2."""
+    p, pp = _in(p)
+    n = p.size // 8
+    out, op = _out(p.shape[:-1] + (3, 3, 2))
+    _load().wdo_decode_link8(n, pp, op)
+    return out
+
+
+def gauge_fix_temporal(dims, U):
+    """(U in temporal gauge, g [V,3,3,2]) with U'_mu(x) = g(x) U_mu(x) g(x+mu)^dagger."""
+    U, up = _in(U)
+    V = _vol(dims)
+    Uo, uop = _out((V, 4, 3, 3, 2))
+    g, gp = _out((V, 3, 3, 2))
+    d, dp = _dims(dims)
+    _load().wdo_gauge_fix_temporal(dp, up, uop, gp)
+    return Uo, g
+
+
+def gauge_rotate_spinor(dims, g, psi, adjoint=False):
+    """psi'(x) = g(x) psi(x) (or g(x)^dagger psi(x)); psi [nrhs?, V, 4, 3, 2]."""
+    g, gp = _in(g)
+    psi, pp = _in(psi)
+    V = _vol(dims)
+    nrhs = psi.size // (V * 24)
+    out, op = _out(psi.shape)
+    d, dp = _dims(dims)
+    _load().wdo_gauge_rotate_spinor(dp, gp, pp, op, nrhs, 1 if adjoint else 0)
     return out

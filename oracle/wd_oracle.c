@@ -497,3 +497,121 @@ void wdo_decode_link16(int kind, int64_t n, const uint16_t *q, double *out) {
   for (int64_t i = 0; i < n; ++i)
     out[i] = kind == 0 ? (double)((float)(int16_t)q[i] * (1.0f / 32767.0f)) : (double)f16_to_f32(q[i]);
 }
+
+/* ---- 8-real link parametrization (Appendix A.2) --------------------------- */
+/*
+ * An SU(3) matrix with rows a, b, c is stored as the 8 reals
+ *   (Re a2, Im a2, Re a3, Im a3, Re b1, Im b1, arg a1, arg c1)
+ * (columns numbered 1..3 as in the paper).  Rebuilding it:
+ *   |a1| = sqrt(1 - |a2|^2 - |a3|^2)            (the first row is a unit vector)
+ *   |c1| = sqrt(1 - |a1|^2 - |b1|^2)            (so is the first column)
+ *   a1, c1 from their moduli and phases
+ *   N  = sqrt(|a2|^2 + |a3|^2)
+ *   b' = (0, -conj(a3), conj(a2)) / N,  c' = conj(a x b') = (N, -conj(a1) a2 / N, -conj(a1) a3 / N)
+ *   b  = p1 b' + p2 c',  c = -conj(p2) b' + conj(p1) c',  p1 = conj(c1) / N,  p2 = b1 / N
+ * i.e. an SU(2) rotation of the plane orthogonal to a (b1 = N p2, conj(c1) = N p1).
+ * A negative argument of either square root (rounding in low precision) is
+ * taken as zero, the paper's stabilisation.  Singular at N = 0 (|a1| = 1).
+ */
+void wdo_encode_link8(int64_t n, const double *U, double *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const cplx *u = (const cplx *)(U + 18 * i);
+    double *o = out + 8 * i;
+    o[0] = creal(u[1]); o[1] = cimag(u[1]);   /* a2 */
+    o[2] = creal(u[2]); o[3] = cimag(u[2]);   /* a3 */
+    o[4] = creal(u[3]); o[5] = cimag(u[3]);   /* b1 */
+    o[6] = carg(u[0]);                        /* arg a1 */
+    o[7] = carg(u[6]);                        /* arg c1 */
+  }
+}
+
+void wdo_decode_link8(int64_t n, const double *in, double *U) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double *p = in + 8 * i;
+    cplx *u = (cplx *)(U + 18 * i);
+    const cplx a2 = p[0] + I * p[1], a3 = p[2] + I * p[3], b1 = p[4] + I * p[5];
+    double s = 1.0 - (cabs(a2) * cabs(a2) + cabs(a3) * cabs(a3));
+    const double ma1 = s > 0.0 ? sqrt(s) : 0.0;
+    const cplx a1 = ma1 * (cos(p[6]) + I * sin(p[6]));
+    s = 1.0 - (ma1 * ma1 + cabs(b1) * cabs(b1));
+    const double mc1 = s > 0.0 ? sqrt(s) : 0.0;
+    const cplx c1 = mc1 * (cos(p[7]) + I * sin(p[7]));
+    const double N = sqrt(cabs(a2) * cabs(a2) + cabs(a3) * cabs(a3));
+    const cplx bp[3] = {0.0, -conj(a3) / N, conj(a2) / N};
+    const cplx cp[3] = {N, -conj(a1) * a2 / N, -conj(a1) * a3 / N};
+    const cplx p1 = conj(c1) / N, p2 = b1 / N;
+    const cplx a[3] = {a1, a2, a3};
+    for (int k = 0; k < 3; ++k) {
+      u[k] = a[k];
+      u[3 + k] = p1 * bp[k] + p2 * cp[k];
+      u[6 + k] = -conj(p2) * bp[k] + conj(p1) * cp[k];
+    }
+  }
+}
+
+/* ---- temporal gauge (the gauge-fixing trick of Section 4.3) --------------- */
+/*
+ * g(x,0) = 1, g(x,t+1) = g(x,t) U_t(x,t) along every time line; then
+ * U'_mu(x) = g(x) U_mu(x) g(x+mu)^dagger.  Every temporal link becomes the
+ * unit matrix except on the last time slice, where U'_t(x, Lt-1) is the
+ * product of the time line's links (the boundary term).  Spinors transform
+ * as psi'(x) = g(x) psi(x), so D[U'] = G D[U] G^dagger.
+ */
+static void mat_mul(const cplx *A, const cplx *B, cplx *C) {   /* C = A B */
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cplx s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+void wdo_gauge_fix_temporal(const int32_t dims[4], const double *U, double *Uout, double *g) {
+  const lat_t l = make_lat(dims, 0);
+  const cplx *u = (const cplx *)U;
+  cplx *uo = (cplx *)Uout, *G = (cplx *)g;
+  const int64_t V3 = (int64_t)l.L[0] * l.L[1] * l.L[2];
+  for (int64_t s = 0; s < V3; ++s) {
+    cplx *g0 = G + 9 * s;                 /* t = 0: lex = s */
+    for (int k = 0; k < 9; ++k) g0[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    for (int t = 0; t + 1 < l.L[3]; ++t)
+      mat_mul(G + 9 * (s + V3 * t), u + 9 * (4 * (s + V3 * t) + 3), G + 9 * (s + V3 * (t + 1)));
+  }
+#pragma omp parallel for
+  for (int64_t i = 0; i < l.V; ++i) {
+    int x[4];
+    coords_of(&l, i, x);
+    for (int mu = 0; mu < 4; ++mu) {
+      int y[4] = {x[0], x[1], x[2], x[3]};
+      y[mu] = (y[mu] + 1) % l.L[mu];
+      const cplx *gx = G + 9 * i, *gy = G + 9 * lex_of(&l, y);
+      cplx tmp[9], gyd[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gyd[3 * a + b] = conj(gy[3 * b + a]);
+      mat_mul(gx, u + 9 * (4 * i + mu), tmp);
+      mat_mul(tmp, gyd, uo + 9 * (4 * i + mu));
+    }
+  }
+}
+
+/* psi'(x) = g(x) psi(x) (adjoint != 0: g(x)^dagger psi(x)), full lattice, nrhs fields. */
+void wdo_gauge_rotate_spinor(const int32_t dims[4], const double *g, const double *in, double *out,
+                             int nrhs, int adjoint) {
+  const lat_t l = make_lat(dims, 0);
+  const cplx *G = (const cplx *)g;
+  for (int r = 0; r < nrhs; ++r) {
+    const cplx *src = (const cplx *)in + (int64_t)r * l.V * 12;
+    cplx *dst = (cplx *)out + (int64_t)r * l.V * 12;
+#pragma omp parallel for
+    for (int64_t i = 0; i < l.V; ++i)
+      for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) {
+          cplx acc = 0.0;
+          for (int b = 0; b < 3; ++b) {
+            const cplx m = adjoint ? conj(G[9 * i + 3 * b + a]) : G[9 * i + 3 * a + b];
+            acc += m * src[12 * i + 3 * s + b];
+          }
+          dst[12 * i + 3 * s + a] = acc;
+        }
+  }
+}

@@ -368,3 +368,81 @@ def test_link16_encoding_properties(kind):
         assert np.all(np.abs(dec - U) <= 0.5 / 32767 + 1e-7)
     else:
         assert np.all(np.abs(dec - U) <= 2.0 ** -11 * np.abs(U) + 2.0 ** -25)
+
+
+# ---- 8-real links (Appendix A.2) and the temporal gauge (Section 4.3) ----------------
+
+def _cx(U):
+    return U[..., 0] + 1j * U[..., 1]
+
+
+@pytest.mark.parametrize("eps", [0.3, 1.0, 3.0])
+def test_link8_round_trip_restores_the_matrix(eps):
+    U = wdinputs.su3_random(2000, eps, 41)
+    p = oracle.encode_link8(U)
+    assert p.shape == (2000, 8)
+    R = oracle.decode_link8(p)
+    assert np.abs(R - U).max() < 1e-12
+
+
+def test_link8_rebuilds_special_unitary_matrices_from_any_parameters():
+    """For any a2, a3 (|a2|^2 + |a3|^2 < 1), b1 (|b1|^2 <= |a2|^2 + |a3|^2) and
+    phases, the rebuilt matrix is in SU(3) and carries the given entries; a
+    sign slip in b', c' or the plane rotation breaks unitarity or the
+    determinant."""
+    rng = np.random.default_rng(5)
+    n = 500
+    a23 = rng.normal(size=(n, 4))
+    a23 *= (rng.uniform(0.05, 0.95, n) / np.linalg.norm(a23, axis=1))[:, None]
+    N = np.linalg.norm(a23, axis=1)
+    ang = rng.uniform(0, 2 * np.pi, n)
+    b1 = (N * rng.uniform(0, 1, n))[:, None] * np.stack([np.cos(ang), np.sin(ang)], 1)
+    p = np.concatenate([a23, b1, rng.uniform(-np.pi, np.pi, (n, 2))], axis=1)
+    M = _cx(oracle.decode_link8(p))
+    eye = np.eye(3)
+    assert np.abs(M @ np.conj(np.swapaxes(M, 1, 2)) - eye).max() < 1e-13
+    assert np.abs(np.linalg.det(M) - 1).max() < 1e-13
+    assert np.allclose(M[:, 0, 1], p[:, 0] + 1j * p[:, 1]) and np.allclose(M[:, 0, 2], p[:, 2] + 1j * p[:, 3])
+    assert np.allclose(M[:, 1, 0], p[:, 4] + 1j * p[:, 5])
+    assert np.allclose(np.angle(M[:, 0, 0]), np.angle(np.exp(1j * p[:, 6])))
+    assert np.allclose(np.angle(M[:, 2, 0]), np.angle(np.exp(1j * p[:, 7])))
+
+
+def test_link8_negative_square_root_argument_is_taken_as_zero():
+    p = np.array([[0.8, 0.0, 0.0, 0.6000001, 0.0, 0.0, 0.3, 0.2]])
+    M = _cx(oracle.decode_link8(p))
+    assert np.all(np.isfinite(M))
+    assert M[0, 0, 0] == 0.0 and M[0, 2, 0] != 0.0
+
+
+def test_temporal_gauge_makes_time_links_unit_but_on_the_last_slice():
+    dims = (4, 2, 4, 6)
+    U = wdinputs.gauge_random(dims, 0.5, 17)
+    Uf, g = oracle.gauge_fix_temporal(dims, U)
+    Ut = _cx(Uf.reshape(dims[::-1] + (4, 3, 3, 2))[..., 3, :, :, :])
+    assert np.abs(Ut[:-1] - np.eye(3)).max() < 1e-13
+    # the last slice carries the time line's product: same trace as the ordered product
+    Uo = _cx(U.reshape(dims[::-1] + (4, 3, 3, 2))[..., 3, :, :, :])
+    P = np.broadcast_to(np.eye(3, dtype=complex), Uo.shape[1:]).copy()
+    for t in range(dims[3]):
+        P = P @ Uo[t]
+    assert np.abs(np.trace(Ut[-1], axis1=-2, axis2=-1) - np.trace(P, axis1=-2, axis2=-1)).max() < 1e-12
+    G = _cx(g)
+    assert np.abs(G @ np.conj(np.swapaxes(G, -1, -2)) - np.eye(3)).max() < 1e-13
+    # the links stay in SU(3)
+    M = _cx(Uf).reshape(-1, 3, 3)
+    assert np.abs(np.linalg.det(M) - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize("tap", [True, False])
+def test_temporal_gauge_rotation_is_a_similarity_transform_of_d(tap):
+    """D[U'] (G psi) = G (D[U] psi), with the antiperiodic sign untouched."""
+    dims = (4, 2, 4, 6)
+    U = wdinputs.gauge_random(dims, 0.5, 18)
+    Uf, g = oracle.gauge_fix_temporal(dims, U)
+    psi = wdinputs.spinor_gaussian(dims, 19)
+    lhs = oracle.dslash_full(dims, Uf, oracle.gauge_rotate_spinor(dims, g, psi), antiperiodic_t=tap)
+    rhs = oracle.gauge_rotate_spinor(dims, g, oracle.dslash_full(dims, U, psi, antiperiodic_t=tap))
+    assert np.abs(lhs - rhs).max() < 1e-12
+    back = oracle.gauge_rotate_spinor(dims, g, oracle.gauge_rotate_spinor(dims, g, psi), adjoint=True)
+    assert np.abs(back - psi).max() < 1e-13
