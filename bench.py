@@ -117,6 +117,7 @@ def parse():
     ap.add_argument("--dims", default="x".join(map(str, DIMS)))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-defect-correction", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--cpu-sample-sites", type=int, default=200000,
                     help="output sites of the oracle dslash timed for the CPU baseline")
@@ -198,6 +199,25 @@ def main():
     step_bytes = Vh * (n_it * bicgstab_iter_bytes(inner, NRHS) + n_ru * ru_bytes(inner, NRHS)
                        + prepare_bytes(NRHS))
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    # ---- the same batch by defect correction (Algorithm 1), inner tolerance = delta ----
+    dc = None
+    if not args.no_defect_correction:
+        pdc = wd.solve_params(tol=1e-12, maxiter=20000, inner=inner, delta=0.1, nrhs=NRHS, use_graph=True,
+                              restart=True)
+        xdc = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            stdc, infdc = wd.bicgstab_solve(gauge, KAPPA, xdc, b, pdc, ws, stream)
+        torch.cuda.synchronize()
+        tdc = time.perf_counter() - t2
+        dc = {"batch_s": round(tdc, 3), "status": stdc, "iters_max": max(i["iters"] for i in infdc),
+              "restarts_max": max(i["reliable_updates"] for i in infdc),
+              "true_rel_resid_max": max(i["true_rel_resid"] for i in infdc),
+              "time_vs_reliable_updates": round(tdc / (ms_per_step * 1e-3), 3)}
+        log(f"defect correction: {dc}")
+        del xdc
 
     # ---- FP64 single-RHS reference solve (same source 0) ----
     fp64 = None
@@ -366,7 +386,8 @@ def main():
                              "iters_mixed_max": max(iters), "reliable_updates_max": n_ru,
                              "iters_fp64": fp64["iters"] if fp64 else None,
                              "true_rel_resid_max": worst_res,
-                             "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None},
+                             "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None,
+                             "defect_correction": dc},
         "dslash_single_rhs": table,
         "copy_GBps": round(copy_gbs, 1),
         "serve": serve,

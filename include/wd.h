@@ -110,6 +110,39 @@ wd_status wd_gauge_create(const wd_lattice *lat, const double *U_dev, uint32_t p
                           void *dev_buf, size_t bytes, void *stream, wd_gauge **out);
 void wd_gauge_destroy(wd_gauge *g);
 
+/* Link compression and temporal gauge (Section 4.3, Appendix A). */
+#define WD_RECON_12 12      /* rows a, b; c = (a x b)^* (Appendix A.1) */
+#define WD_RECON_8 8        /* Re/Im a2, a3, b1 and the phases of a1, c1 (Appendix A.2); the
+                               16-bit formats store the phases divided by pi.  Singular where
+                               |a1| = 1; less accurate than WD_RECON_12 */
+#define WD_GAUGE_TEMPORAL 1u /* the field is in temporal gauge: U_t(x) = 1 for t < Lt - 1;
+                               those links are not read (wd_gauge_fix_temporal makes such a
+                               field) */
+
+/* Bytes of dev_buf for wd_gauge_create_ex (recon 12 or 8; flags as below). */
+size_t wd_gauge_bytes_ex(const wd_lattice *lat, uint32_t prec_mask, int32_t recon, uint32_t flags);
+
+/* wd_gauge_create with a link format and flags.  With WD_GAUGE_TEMPORAL the
+ * temporal links of t < Lt - 1 are checked (max-norm distance to 1 at most
+ * 1e-10, else WD_EINVAL); the check synchronises the stream.  Every
+ * operator and solver on the handle then uses the unit matrix there. */
+wd_status wd_gauge_create_ex(const wd_lattice *lat, const double *U_dev, uint32_t prec_mask,
+                             int32_t recon, uint32_t flags, void *dev_buf, size_t bytes, void *stream,
+                             wd_gauge **out);
+
+/* Temporal gauge fixing in FP64 (Section 4.3): g(x, 0) = 1, g(x, t+1) =
+ * g(x, t) U_t(x, t), U_out_mu(x) = g(x) U_mu(x) g(x + mu)^dagger.  U_in,
+ * U_out: device [V][4][3][3][2] (may alias); g_out: device [V][3][3][2].
+ * D[U_out] = G D[U_in] G^dagger, so solve with G b and rotate the solution
+ * back with G^dagger (wd_gauge_rotate_spinor).  Asynchronous on stream. */
+wd_status wd_gauge_fix_temporal(const wd_lattice *lat, const double *U_in, double *U_out, double *g_out,
+                                void *stream);
+
+/* out(x) = g(x) in(x) (adjoint: g(x)^dagger in(x)) for nrhs canonical
+ * full-lattice spinors (device, [nrhs][V][4][3][2]; out may alias in). */
+wd_status wd_gauge_rotate_spinor(const wd_lattice *lat, const double *g, double *out, const double *in,
+                                 int32_t nrhs, int32_t adjoint, void *stream);
+
 /* ---- spinor fields ------------------------------------------------------------ */
 
 /* Device bytes of one encoded parity field with nrhs right-hand sides. */
@@ -178,6 +211,11 @@ typedef struct {
                           (needs a non-NULL stream) */
   int32_t check_every; /* reserved, must be 0 or 1 */
   int32_t x0_given;    /* reserved, must be 0 */
+  int32_t restart;     /* 0: reliable updates (Algorithm 2), the Krylov space is kept across
+                          updates.  1: defect correction (Algorithm 1): each update ends an
+                          inner solve, whose tolerance relative to the residual it started
+                          from is delta (> 0), and the next inner solve restarts the Krylov
+                          recurrence from the new FP64 residual */
 } wd_solve_params;
 
 typedef struct {

@@ -17,7 +17,7 @@ __all__ = [
     "Lattice", "WDError", "Gauge", "PREC", "WD_FP64", "WD_FP32", "WD_HALF_I16", "WD_HALF_F16",
     "lattice", "prec_of", "wd_gauge_bytes", "wd_spinor_bytes", "new_field", "wd_spinor_encode",
     "wd_spinor_decode", "wd_spinor_encode_full", "wd_spinor_decode_full", "wilson_dslash",
-    "wilson_mat_pc", "mdagm",
+    "wilson_mat_pc", "mdagm", "gauge_fix_temporal", "wd_gauge_rotate_spinor", "WD_GAUGE_TEMPORAL",
 ]
 
 
@@ -46,22 +46,31 @@ def new_field(lat: Lattice, prec, nrhs: int = 1, device="cuda"):
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
-class Gauge:
-    """A resident gauge field: device buffer (torch) + library handle."""
+WD_GAUGE_TEMPORAL = 1
 
-    def __init__(self, lat: Lattice, U_dev, precs=("fp64", "fp32", "i16", "f16"), stream=None):
+
+class Gauge:
+    """A resident gauge field: device buffer (torch) + library handle.
+
+    recon: 12 or 8 reals per stored link; temporal: the field is in temporal
+    gauge (see gauge_fix_temporal) and the unit time links are not read."""
+
+    def __init__(self, lat: Lattice, U_dev, precs=("fp64", "fp32", "i16", "f16"), stream=None, recon=12,
+                 temporal=False):
         import torch
         self.lat = lat
         self.mask = 0
         for p in precs:
             self.mask |= 1 << prec_of(p)
-        nbytes = wd_gauge_bytes(lat, self.mask)
+        self.recon = recon
+        self.flags = WD_GAUGE_TEMPORAL if temporal else 0
+        nbytes = lib().wd_gauge_bytes_ex(ctypes.byref(lat), self.mask, recon, self.flags)
         if nbytes == 0:
-            raise WDError(-1, "Gauge", "invalid lattice or precision mask")
+            raise WDError(-1, "Gauge", "invalid lattice, precision mask, recon or flags")
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device=U_dev.device)
         h = ctypes.c_void_p()
-        check(lib().wd_gauge_create(ctypes.byref(lat), ptr(U_dev), self.mask, ptr(self.buf), nbytes,
-                                    stream_ptr(stream), ctypes.byref(h)), "wd_gauge_create")
+        check(lib().wd_gauge_create_ex(ctypes.byref(lat), ptr(U_dev), self.mask, recon, self.flags, ptr(self.buf),
+                                       nbytes, stream_ptr(stream), ctypes.byref(h)), "wd_gauge_create_ex")
         self.handle = h
 
     def close(self):
@@ -74,6 +83,22 @@ class Gauge:
             self.close()
         except Exception:
             pass
+
+
+def gauge_fix_temporal(lat: Lattice, U_dev, stream=None):
+    """(U in temporal gauge, g) as new device tensors: U'_mu(x) = g(x) U_mu(x) g(x+mu)^dagger."""
+    import torch
+    V = int(U_dev.numel() // 72)
+    Uo = torch.empty_like(U_dev)
+    g = torch.empty((V, 3, 3, 2), dtype=torch.float64, device=U_dev.device)
+    check(lib().wd_gauge_fix_temporal(ctypes.byref(lat), ptr(U_dev), ptr(Uo), ptr(g), stream_ptr(stream)),
+          "wd_gauge_fix_temporal")
+    return Uo, g
+
+
+def wd_gauge_rotate_spinor(lat: Lattice, g, out, inp, nrhs: int = 1, adjoint: bool = False, stream=None):
+    return check(lib().wd_gauge_rotate_spinor(ctypes.byref(lat), ptr(g), ptr(out), ptr(inp), nrhs,
+                                              1 if adjoint else 0, stream_ptr(stream)), "wd_gauge_rotate_spinor")
 
 
 def wd_spinor_encode(lat, prec, nrhs, field, canon, stream=None):
@@ -121,9 +146,13 @@ WD_SOLVER_BICGSTAB, WD_SOLVER_CG = 0, 1
 SOLVER = {"bicgstab": WD_SOLVER_BICGSTAB, "cg": WD_SOLVER_CG}
 
 
-def solve_params(tol=1e-12, maxiter=10000, inner="fp64", delta=0.1, nrhs=1, use_graph=False) -> SolveParams:
+def solve_params(tol=1e-12, maxiter=10000, inner="fp64", delta=0.1, nrhs=1, use_graph=False,
+                 restart=False) -> SolveParams:
+    """restart=False: reliable updates (Algorithm 2); True: defect correction
+    (Algorithm 1) with inner tolerance delta."""
     return SolveParams(tol=tol, maxiter=maxiter, inner=prec_of(inner), delta=delta, nrhs=nrhs,
-                       use_graph=1 if use_graph else 0, check_every=0, x0_given=0)
+                       use_graph=1 if use_graph else 0, check_every=0, x0_given=0,
+                       restart=1 if restart else 0)
 
 
 def wd_solve_workspace_bytes(lat: Lattice, params: SolveParams, solver) -> int:
@@ -162,10 +191,10 @@ def cg_solve(gauge: Gauge, kappa: float, x, b, params: SolveParams, workspace, s
 
 
 def solve_full(solver: str, gauge: Gauge, lat: Lattice, kappa: float, b, tol=1e-12, inner="fp64",
-               delta=0.1, nrhs=1, use_graph=False, maxiter=10000, stream=None):
+               delta=0.1, nrhs=1, use_graph=False, maxiter=10000, stream=None, restart=False):
     """Allocate x and the workspace (torch) and run bicgstab_solve / cg_solve."""
     import torch
-    params = solve_params(tol, maxiter, inner, delta, nrhs, use_graph)
+    params = solve_params(tol, maxiter, inner, delta, nrhs, use_graph, restart)
     ws = new_workspace(lat, params, solver, b.device)
     x = torch.zeros_like(b)
     fn = bicgstab_solve if solver == "bicgstab" else cg_solve

@@ -58,6 +58,14 @@ def lib():
         L.wd_gauge_bytes.restype = sz
         L.wd_gauge_create.argtypes = [lp, vp, u32, vp, sz, vp, ctypes.POINTER(vp)]
         L.wd_gauge_create.restype = i32
+        L.wd_gauge_bytes_ex.argtypes = [lp, u32, i32, u32]
+        L.wd_gauge_bytes_ex.restype = sz
+        L.wd_gauge_create_ex.argtypes = [lp, vp, u32, i32, u32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.wd_gauge_create_ex.restype = i32
+        L.wd_gauge_fix_temporal.argtypes = [lp, vp, vp, vp, vp]
+        L.wd_gauge_fix_temporal.restype = i32
+        L.wd_gauge_rotate_spinor.argtypes = [lp, vp, vp, vp, i32, i32, vp]
+        L.wd_gauge_rotate_spinor.restype = i32
         L.wd_gauge_destroy.argtypes = [vp]
         L.wd_gauge_destroy.restype = None
         L.wd_spinor_bytes.argtypes = [lp, i32, i32]

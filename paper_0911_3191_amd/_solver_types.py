@@ -7,7 +7,7 @@ import ctypes
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("delta", ctypes.c_double), ("nrhs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("x0_given", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("x0_given", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

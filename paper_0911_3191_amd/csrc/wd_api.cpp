@@ -24,13 +24,7 @@ wd_status fail(wd_status code, const std::string& msg) {
 
 // Chunk arrays are padded to a multiple of 64 sites (one wavefront) so that
 // every chunk array starts 1 KiB-aligned relative to the field base.
-int64_t field_stride(int64_t Vh) {
-  static const int64_t pad = [] {
-    const char* e = std::getenv("WD_STRIDE_PAD");
-    return e ? std::max<int64_t>(0, std::atoll(e)) : int64_t(0);
-  }();
-  return (Vh + 63) / 64 * 64 + pad;
-}
+int64_t field_stride(int64_t Vh) { return (Vh + 63) / 64 * 64; }
 
 Geom make_geom(const wd_lattice& lat) {
   Geom g;
@@ -110,27 +104,35 @@ const char* wd_last_error(void) { return g_last_error.c_str(); }
 
 const char* wd_version(void) { return "wdslash 0.1 (gfx950)"; }
 
-size_t wd_gauge_bytes(const wd_lattice* lat, uint32_t prec_mask) {
+size_t wd_gauge_bytes_ex(const wd_lattice* lat, uint32_t prec_mask, int32_t recon, uint32_t flags) {
   if (check_lattice(lat) != WD_OK) return 0;
   if (prec_mask == 0 || (prec_mask & ~0xfu)) return 0;
+  if ((recon != 12 && recon != 8) || (flags & ~WD_GAUGE_TEMPORAL)) return 0;
   const Geom g = make_geom(*lat);
   size_t b = 0;
   for (int p = 0; p < 4; ++p)
-    if (prec_mask & WD_PREC_MASK(p)) b += static_cast<size_t>(8) * g.stride * link_bytes(p);
+    if (prec_mask & WD_PREC_MASK(p)) b += static_cast<size_t>(8) * g.stride * link_bytes(p, recon);
+  if (flags & WD_GAUGE_TEMPORAL) b += 256;  // the temporal-gauge check's result
   return b;
 }
 
-wd_status wd_gauge_create(const wd_lattice* lat, const double* U_dev, uint32_t prec_mask,
-                          void* dev_buf, size_t bytes, void* stream, wd_gauge** out) {
+size_t wd_gauge_bytes(const wd_lattice* lat, uint32_t prec_mask) {
+  return wd_gauge_bytes_ex(lat, prec_mask, 12, 0);
+}
+
+wd_status wd_gauge_create_ex(const wd_lattice* lat, const double* U_dev, uint32_t prec_mask, int32_t recon,
+                             uint32_t flags, void* dev_buf, size_t bytes, void* stream, wd_gauge** out) {
   g_last_error.clear();
   if (!out) return fail(WD_EINVAL, "out is NULL");
   *out = nullptr;
   wd_status st = check_lattice(lat);
   if (st) return st;
   if (prec_mask == 0 || (prec_mask & ~0xfu)) return fail(WD_EINVAL, "invalid precision mask");
+  if (recon != 12 && recon != 8) return fail(WD_EINVAL, "recon must be 12 or 8");
+  if (flags & ~WD_GAUGE_TEMPORAL) return fail(WD_EINVAL, "unknown gauge flags");
   if ((st = check_ptr(U_dev, "U_dev"))) return st;
   if ((st = check_ptr(dev_buf, "dev_buf"))) return st;
-  const size_t need = wd_gauge_bytes(lat, prec_mask);
+  const size_t need = wd_gauge_bytes_ex(lat, prec_mask, recon, flags);
   if (bytes < need)
     return fail(WD_EINVAL, "dev_buf too small: " + std::to_string(bytes) + " < " + std::to_string(need));
   wd_gauge* g = new (std::nothrow) wd_gauge;
@@ -138,21 +140,74 @@ wd_status wd_gauge_create(const wd_lattice* lat, const double* U_dev, uint32_t p
   g->lat = *lat;
   g->geom = make_geom(*lat);
   g->mask = prec_mask;
+  g->recon = recon;
+  g->tgauge = (flags & WD_GAUGE_TEMPORAL) ? 1 : 0;
   char* p = static_cast<char*>(dev_buf);
   for (int q = 0; q < 4; ++q) {
     g->link[q] = nullptr;
     if (prec_mask & WD_PREC_MASK(q)) {
       g->link[q] = p;
-      p += static_cast<size_t>(8) * g->geom.stride * link_bytes(q);
+      p += static_cast<size_t>(8) * g->geom.stride * link_bytes(q, recon);
     }
   }
-  st = hip_status(launch_gauge_encode(g, U_dev, static_cast<hipStream_t>(stream)), "gauge encode");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (g->tgauge) {
+    // the largest distance of a checked temporal link from 1, as double bits
+    auto* dev = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long host = 0;
+    hipError_t e = hipMemsetAsync(dev, 0, sizeof(host), s);
+    if (e == hipSuccess) e = launch_temporal_check(g->geom, U_dev, dev, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, dev, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      delete g;
+      return hip_status(e, "temporal-gauge check");
+    }
+    double dev_max;
+    std::memcpy(&dev_max, &host, sizeof(dev_max));
+    if (!(dev_max <= 1e-10)) {
+      delete g;
+      return fail(WD_EINVAL, "links are not in temporal gauge (max |U_t - 1| = " + std::to_string(dev_max) +
+                                 " off the last time slice)");
+    }
+  }
+  st = hip_status(recon == 8 ? launch_gauge_encode8(g, U_dev, s) : launch_gauge_encode(g, U_dev, s),
+                  "gauge encode");
   if (st) {
     delete g;
     return st;
   }
   *out = g;
   return WD_OK;
+}
+
+wd_status wd_gauge_create(const wd_lattice* lat, const double* U_dev, uint32_t prec_mask, void* dev_buf,
+                          size_t bytes, void* stream, wd_gauge** out) {
+  return wd_gauge_create_ex(lat, U_dev, prec_mask, 12, 0, dev_buf, bytes, stream, out);
+}
+
+wd_status wd_gauge_fix_temporal(const wd_lattice* lat, const double* U_in, double* U_out, double* g_out,
+                                void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if ((st = check_ptr(U_in, "U_in")) || (st = check_ptr(U_out, "U_out")) || (st = check_ptr(g_out, "g_out")))
+    return st;
+  return hip_status(launch_gauge_fix_temporal(make_geom(*lat), U_in, U_out, g_out, static_cast<hipStream_t>(stream)),
+                    "temporal gauge fixing");
+}
+
+wd_status wd_gauge_rotate_spinor(const wd_lattice* lat, const double* g, double* out, const double* in,
+                                 int32_t nrhs, int32_t adjoint, void* stream) {
+  g_last_error.clear();
+  wd_status st = check_lattice(lat);
+  if (st) return st;
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(g, "g")) || (st = check_ptr(out, "out")) ||
+      (st = check_ptr(in, "in")))
+    return st;
+  return hip_status(launch_gauge_rotate(make_geom(*lat), g, in, out, nrhs, adjoint ? 1 : 0,
+                                        static_cast<hipStream_t>(stream)),
+                    "spinor rotation");
 }
 
 void wd_gauge_destroy(wd_gauge* g) { delete g; }

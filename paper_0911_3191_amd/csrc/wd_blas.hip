@@ -342,8 +342,9 @@ __global__ void __launch_bounds__(kBlock) k_reencode(int Vh, FieldView rh, Field
 
 // ---- finalize: partials -> scalars (one block per RHS) ---------------------------------
 struct FinArgs {
-  double delta;  // reliable-update trigger
+  double delta;  // reliable-update trigger (defect correction: inner tolerance)
   double tol;    // target relative residual
+  int restart;   // 1: defect correction (Algorithm 1), 0: reliable updates (Algorithm 2)
 };
 
 __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const double* __restrict__ partials,
@@ -425,7 +426,9 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
         active[rhs] = 0;
         break;
       }
-      s[SC_MMAX] = fmax(s[SC_MMAX], rn);
+      // reliable updates: against the largest |r^| since the last update;
+      // defect correction: against the residual the inner solve started from
+      if (!fa.restart) s[SC_MMAX] = fmax(s[SC_MMAX], rn);
       const int ru = (rn < fa.delta * s[SC_MMAX]) || (rn <= stop);
       f[FL_RU] = ru;
       rumask[rhs] = ru;
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       s[SC_RHO] = v[0];
       s[SC_R2] = v[0];
       s[SC_BETA] = v[0] / s[SC_RHOP];
-      s[SC_MMAX] = fmax(s[SC_MMAX], rn);
+      if (!fa.restart) s[SC_MMAX] = fmax(s[SC_MMAX], rn);
       const int ru = (rn < fa.delta * s[SC_MMAX]) || (rn <= s[SC_TOLN]);
       f[FL_RU] = ru;
       rumask[rhs] = ru;
@@ -467,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
     case FIN_CG_RHO: {  // after a reliable update: new |r^|^2, beta against the old rho
       s[SC_R2] = v[0];
       s[SC_RHO] = v[0];
-      s[SC_BETA] = v[0] / s[SC_RHOP];
+      s[SC_BETA] = fa.restart ? 0.0 : v[0] / s[SC_RHOP];  // defect correction: p = r^
       s[SC_MMAX] = sqrt(v[0]);
       break;
     }
@@ -609,9 +612,9 @@ hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r6
 
 hipError_t solver_finalize(int stage, int nrhs, int nb, const double* partials, double* sc, int* fl,
                            int* active, int* rumask, const int* mask, double delta, double tol,
-                           hipStream_t s) {
+                           int restart, hipStream_t s) {
   k_finalize<<<nrhs, kBlock, 0, s>>>(stage, nb, partials, sc, fl, active, rumask, mask,
-                                     FinArgs{delta, tol});
+                                     FinArgs{delta, tol, restart});
   return hipGetLastError();
 }
 

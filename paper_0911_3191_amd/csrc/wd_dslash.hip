@@ -76,6 +76,7 @@ struct DslashGeom {
   int gslow;            // 1: an XCD sweeps its slab once per RHS group (group slowest)
   int link_nt;          // 1: link loads are marked streaming (read once per launch)
   int out_nt;           // 1: output stores are marked streaming
+  int tgauge;           // 1: temporal links are the unit matrix off the last time slice
 };
 
 // ---- buffer loads --------------------------------------------------------------
@@ -241,12 +242,107 @@ __device__ __forceinline__ void gather_link_aux(const char* links, int64_t strid
   }
 }
 
-// Link of (par, mu) at site i with the launch's cache policy for links.
-template <class S>
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+
+// Link of (par, mu) at site i stored as 8 reals (Appendix A.2): a2, a3, b1 and
+// the phases of a1 and c1 (16-bit formats: phases / pi).  Rebuilt with
+// |a1| = sqrt(1 - |a2|^2 - |a3|^2), |c1| = sqrt(1 - |a1|^2 - |b1|^2) (negative
+// arguments taken as zero), N = sqrt(|a2|^2 + |a3|^2), the plane vectors
+// b' = (0, -a3*, a2*) / N and c' = (N, -a1* a2 / N, -a1* a3 / N), and the
+// rotation b = p1 b' + p2 c', c = -p2* b' + p1* c' with p1 = c1* / N,
+// p2 = b1 / N.
+template <class S, int AUX>
+__device__ __forceinline__ void gather_link8(const char* links, int64_t stride, int par, int mu, int i,
+                                          Link<typename S::real>& L) {
+  using R = typename S::real;
+  constexpr int N8 = (S::prec == WD_FP64) ? 4 : (S::prec == WD_FP32 ? 2 : 1);  // 16-byte chunks
+  const uint32_t cbytes = (uint32_t)(stride * 16);
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc(links + (int64_t)((par * 4 + mu) * N8) * stride * 16, cbytes * N8);
+  const uint32_t vo = (uint32_t)i * 16u;
+  R v[8];
+  if constexpr (S::prec == WD_FP64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 c = __builtin_bit_cast(double2, bload16<AUX>(rs, vo, k * cbytes));
+      v[2 * k] = c.x;
+      v[2 * k + 1] = c.y;
+    }
+  } else if constexpr (S::prec == WD_FP32) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const float4 c = __builtin_bit_cast(float4, bload16<AUX>(rs, vo, k * cbytes));
+      v[4 * k] = c.x;
+      v[4 * k + 1] = c.y;
+      v[4 * k + 2] = c.z;
+      v[4 * k + 3] = c.w;
+    }
+  } else {
+    const uint4 c = bload16<AUX>(rs, vo, 0);
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (S::prec == WD_HALF_I16) {
+        v[2 * j] = (float)(int16_t)(w[j] & 0xffffu) * (1.0f / 32767.0f);
+        v[2 * j + 1] = (float)(int16_t)(w[j] >> 16) * (1.0f / 32767.0f);
+      } else {
+        v[2 * j] = half_lo(w[j]);
+        v[2 * j + 1] = half_hi(w[j]);
+      }
+    }
+    v[6] *= 3.14159265358979323846f;
+    v[7] *= 3.14159265358979323846f;
+  }
+  const cx<R> a2 = {v[0], v[1]}, a3 = {v[2], v[3]}, b1 = {v[4], v[5]};
+  const R n2 = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
+  R t = R(1) - n2;
+  const R ma1 = t > R(0) ? sqrt(t) : R(0);
+  t = R(1) - (ma1 * ma1 + (b1.re * b1.re + b1.im * b1.im));
+  const R mc1 = t > R(0) ? sqrt(t) : R(0);
+  R s1, c1c, s2, c2c;
+  sincos_r(v[6], &s1, &c1c);
+  sincos_r(v[7], &s2, &c2c);
+  const cx<R> a1 = {ma1 * c1c, ma1 * s1}, c1 = {mc1 * c2c, mc1 * s2};
+  const R nn = sqrt(n2);
+  const R rn = R(1) / nn;
+  // plane vectors b' (first entry 0) and c'
+  const cx<R> bp1 = {-a3.re * rn, a3.im * rn}, bp2 = {a2.re * rn, -a2.im * rn};
+  const cx<R> a1c = conj(a1);
+  const cx<R> cp1 = (-rn) * (a1c * a2), cp2 = (-rn) * (a1c * a3);
+  const cx<R> p1 = rn * conj(c1), p2 = rn * b1;
+  const cx<R> p1c = conj(p1), p2c = conj(p2);
+  L.u[0][0] = a1;
+  L.u[0][1] = a2;
+  L.u[0][2] = a3;
+  L.u[1][0] = nn * p2;
+  L.u[1][1] = p1 * bp1 + p2 * cp1;
+  L.u[1][2] = p1 * bp2 + p2 * cp2;
+  L.u[2][0] = nn * p1c;
+  L.u[2][1] = p1c * cp1 - p2c * bp1;
+  L.u[2][2] = p1c * cp2 - p2c * bp2;
+}
+
+template <typename R>
+__device__ __forceinline__ void unit_link(Link<R>& L) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) L.u[a][b] = {a == b ? R(1) : R(0), R(0)};
+}
+
+// Link of (par, mu) at site i in the handle's format, with the launch's cache
+// policy for links.
+template <class S, int RECON>
 __device__ __forceinline__ void gather_link(const DslashGeom& g, const char* links, int par, int mu, int i,
                                             Link<typename S::real>& L) {
-  if (g.link_nt) gather_link_aux<S, kStream>(links, g.stride, par, mu, i, L);
-  else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
+  if constexpr (RECON == 8) {
+    if (g.link_nt) gather_link8<S, kStream>(links, g.stride, par, mu, i, L);
+    else gather_link8<S, 0>(links, g.stride, par, mu, i, L);
+  } else {
+    if (g.link_nt) gather_link_aux<S, kStream>(links, g.stride, par, mu, i, L);
+    else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
+  }
 }
 
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -324,7 +420,7 @@ __device__ __forceinline__ void hop16(Spinor<float>& acc, const Raw16& psi, cons
 }
 
 // Both hops of direction MU for the NR right-hand sides of this thread.
-template <class S, int MU, bool DAGGER, int NR>
+template <class S, int MU, bool DAGGER, int NR, int RECON>
 __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
                                          const char* __restrict__ links, const SpinorBuf<S> (&in)[NR],
                                          const bool (&on)[NR], int p, int cb, int xh, int row,
@@ -351,10 +447,19 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
       flip_b = g.tap && (X[3] == 0);
     }
   }
+  // temporal gauge: U_t is the unit matrix off the last time slice, so the
+  // forward t-hop reads a link only from t = Lt - 1, the backward one only
+  // into t = 0 (elsewhere the unit matrix is applied without a load)
+  bool unit_f = false, unit_b = false;
+  if constexpr (MU == 3) {
+    unit_f = g.tgauge && X[3] != g.L[3] - 1;
+    unit_b = g.tgauge && X[3] != 0;
+  }
   // forward: (1 - gamma_mu) U_x^mu psi(x + mu); adjoint: (1 + gamma_mu)
   {
     Link<R> U;
-    gather_link<S>(g, links, p, MU, cb, U);
+    if (unit_f) unit_link(U);
+    else gather_link<S, RECON>(g, links, p, MU, cb, U);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!on[k]) continue;
@@ -374,7 +479,8 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
   // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
   {
     Link<R> U;
-    gather_link<S>(g, links, 1 - p, MU, nb, U);
+    if (unit_b) unit_link(U);
+    else gather_link<S, RECON>(g, links, 1 - p, MU, nb, U);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!on[k]) continue;
@@ -399,7 +505,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
 //   DOT_OO: |out|^2                  (CG |M p|^2)
 // Right-hand sides whose active flag is 0 are skipped.
-template <class S, bool DAGGER, bool XPAY, int DOT, int NR>
+template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
                                                        FieldView ys, typename S::real a, int p,
@@ -478,10 +584,10 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     SpinorBuf<S> ib[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0);
-    hop_pair<S, 0, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 1, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 2, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 3, DAGGER, NR>(acc, g, links, ib, on, p, cb, xh, row, X, one);
+    hop_pair<S, 0, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
+    hop_pair<S, 1, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
+    hop_pair<S, 2, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
+    hop_pair<S, 3, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
@@ -570,6 +676,7 @@ static DslashGeom make_dgeom(const Geom& geo, int nrhs, const LaunchCfg& c) {
   g.gslow = c.gslow;
   g.link_nt = c.link_nt;
   g.out_nt = c.out_nt;
+  g.tgauge = 0;
   g.slab = (geo.L[2] % 8 == 0) ? 1 : 0;
   g.nsub = (c.nsub >= 1 && geo.L[1] % c.nsub == 0) ? c.nsub : 1;
   g.sub_plane = geo.Lxh * (geo.L[1] / g.nsub);
@@ -600,28 +707,31 @@ static size_t lds_for(int wgs) {
   return per > 63488 ? 63488 : per;  // below the 64 KiB per-workgroup limit with the static LDS
 }
 
-template <class S, bool DAGGER, bool XPAY, int NR>
+template <class S, bool DAGGER, bool XPAY, int NR, int RECON>
 static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
                        const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
                        typename S::real a, int p, const int* active, double* partials) {
   switch (dot) {
     case DOT_YO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     case DOT_OX:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     case DOT_OO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
       break;
     default:
-      dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+      dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
   }
 }
 
-template <class S, int NR>
-static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
-  const DslashGeom g = make_dgeom(gg->geom, d.out.nrhs, c);
+template <class S, int NR, int RECON>
+static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
+  LaunchCfg c = cfg;
+  c.nr = NR;  // the RHS slots of the kernel actually launched
+  DslashGeom g = make_dgeom(gg->geom, d.out.nrhs, c);
+  g.tgauge = gg->tgauge;
   const char* links = static_cast<const char*>(gg->link[S::prec]);
   const unsigned grid = grid_blocks(g);
   FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
@@ -629,21 +739,29 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   const R ar = static_cast<R>(d.a);
   const int dot = d.xpay ? d.dot : DOT_NONE;
   if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true, NR>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, true, false, NR>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, true, true, NR, RECON>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, true, false, NR, RECON>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   } else {
-    if (d.xpay) launch_dot<S, false, true, NR>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, false, false, NR>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, false, true, NR, RECON>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, false, false, NR, RECON>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   }
 }
 
+// Threads carry at least two RHS slots: with one, the compiler keeps every
+// gather of a site in flight and runs out of registers (a single RHS leaves
+// the second slot empty).  8-real links are built for two slots only (their
+// rebuild is long; wider shapes gain little when links are a small part of
+// the bytes).
 template <class S>
 static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
+  if (gg->recon == 8) {
+    launch_nr<S, 2, 8>(gg, d, c, s);
+    return;
+  }
   switch (c.nr) {
-    case 2: launch_nr<S, 2>(gg, d, c, s); break;
-    case 3: launch_nr<S, 3>(gg, d, c, s); break;
-    case 4: launch_nr<S, 4>(gg, d, c, s); break;
-    default: launch_nr<S, 1>(gg, d, c, s); break;
+    case 3: launch_nr<S, 3, 12>(gg, d, c, s); break;
+    case 4: launch_nr<S, 4, 12>(gg, d, c, s); break;
+    default: launch_nr<S, 2, 12>(gg, d, c, s); break;
   }
 }
 

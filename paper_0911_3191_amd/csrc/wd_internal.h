@@ -28,8 +28,11 @@ int64_t field_stride(int64_t Vh);
 // chunks a site's 24 spinor reals occupy.
 inline int spinor_chunks(wd_prec p) { return p == WD_FP64 ? 12 : (p == WD_FP32 ? 6 : 3); }
 inline bool is_half(wd_prec p) { return p == WD_HALF_I16 || p == WD_HALF_F16; }
-// Bytes per link (12 reals).
-inline int link_bytes(wd_prec p) { return p == WD_FP64 ? 96 : (p == WD_FP32 ? 48 : 24); }
+// Bytes per stored link: 12 reals (Appendix A.1) or 8 reals (Appendix A.2).
+inline int link_bytes(wd_prec p, int recon = 12) {
+  const int reals = recon == 8 ? 8 : 12;
+  return reals * (p == WD_FP64 ? 8 : (p == WD_FP32 ? 4 : 2));
+}
 
 // A parity spinor field: nrhs right-hand sides, chunk arrays of `stride`
 // 16-byte elements each, laid out [rhs][chunk][site]; 16-bit formats append
@@ -48,6 +51,8 @@ struct wd_gauge {
   wd_lattice lat;
   wd::Geom geom;
   uint32_t mask;
+  int recon;      // 12 or 8 reals per link
+  int tgauge;     // 1: temporal links are the unit matrix except on the last time slice
   void* link[4];  // per precision: [parity][mu][chunk][site]
 };
 
@@ -102,6 +107,12 @@ hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, i
                          int dagger, const Field* xpay_src, double a, hipStream_t s);
 
 hipError_t launch_gauge_encode(const wd_gauge* g, const double* U, hipStream_t s);
+// 8-real links, temporal gauge (wd_gauge.hip)
+hipError_t launch_gauge_encode8(const wd_gauge* g, const double* U, hipStream_t s);
+hipError_t launch_temporal_check(const Geom& geo, const double* U, unsigned long long* dev, hipStream_t s);
+hipError_t launch_gauge_fix_temporal(const Geom& geo, const double* U, double* Uo, double* g, hipStream_t s);
+hipError_t launch_gauge_rotate(const Geom& geo, const double* g, const double* in, double* out, int nrhs,
+                               int adjoint, hipStream_t s);
 
 // canonical parity spinors [nrhs][Vh][24] <-> field
 hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,
@@ -158,9 +169,11 @@ hipError_t blas_residual(const Geom& g, Field r64, Field b64, const int* mask, d
 hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s);
 hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
                          const int* mask, double* partials, hipStream_t s);
+// restart = 1 (defect correction): the update trigger compares |r^| with the
+// residual the inner solve started from, and CG restarts with beta = 0.
 hipError_t solver_finalize(int stage, int nrhs, int nb, const double* partials, double* sc, int* fl,
                            int* active, int* rumask, const int* mask, double delta, double tol,
-                           hipStream_t s);
+                           int restart, hipStream_t s);
 hipError_t solver_cg_tighten(int nrhs, double* sc, const int* fl, const int* mask, double tol,
                              hipStream_t s);
 hipError_t solver_init_flags(int nrhs, int* fl, int* active, int* rumask, hipStream_t s);

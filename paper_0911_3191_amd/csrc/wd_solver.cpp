@@ -118,7 +118,8 @@ static hipError_t fin(wd_solver* h, int stage, const int* mask) {
   // the stages that follow a dslash with a fused dot read the dslash's partial records
   const bool after_dslash = stage == FIN_BICG_ALPHA || stage == FIN_BICG_OMEGA || stage == FIN_CG_ALPHA;
   return solver_finalize(stage, h->nrhs, after_dslash ? h->nb_dslash : h->nb, h->partials, h->sc,
-                         h->fl, h->active, h->rumask, mask, h->prm.delta, h->prm.tol, h->s);
+                         h->fl, h->active, h->rumask, mask, h->prm.delta, h->prm.tol, h->prm.restart,
+                         h->s);
 }
 
 #define WD_TRY(expr)                         \
@@ -161,13 +162,21 @@ static hipError_t true_residual(wd_solver* h, const int* mask) {
 }
 
 // Re-seed the inner residual from the FP64 one (and zero x^) for the RHS in rumask.
+// Defect correction restarts BiCGstab there: new shadow residual, p = v = 0
+// and the scalars of a first iteration.  (CG restarts through beta = 0 at
+// FIN_CG_RHO, so that the p update after the step sets p = r^.)
 static hipError_t reseed(wd_solver* h, bool first) {
   const Geom& g = h->geom;
   const wd_prec P = h->prm.inner;
   if (h->kind == WD_SOLVER_BICGSTAB) {
-    if (first) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, h->r, h->rumask, h->s));  // r~ = r_0
+    const bool fresh = first || h->prm.restart;
+    if (fresh) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, h->r, h->rumask, h->s));  // r~ = r
+    if (!first && h->prm.restart) {
+      WD_TRY(blas_zero(g, P, h->p, h->rumask, h->s));
+      WD_TRY(blas_zero(g, P, h->v, h->rumask, h->s));
+    }
     WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->r, &h->rt, h->rumask, h->partials, h->s));
-    WD_TRY(fin(h, first ? FIN_BICG_INIT : FIN_RHO, h->rumask));
+    WD_TRY(fin(h, fresh ? FIN_BICG_INIT : FIN_RHO, h->rumask));
   } else {
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
     // normal-equation residual M_hat^dag r in FP64
@@ -254,7 +263,6 @@ namespace {
 wd_status validate(int kind, const wd_gauge* g, double kappa, const void* x, const void* b,
                    const wd_solve_params* prm, const void* ws, size_t ws_bytes) {
   if (kind != WD_SOLVER_BICGSTAB && kind != WD_SOLVER_CG) return fail(WD_EINVAL, "unknown solver");
-  if (!g) return fail(WD_EINVAL, "gauge handle is NULL");
   if (!prm) return fail(WD_EINVAL, "params is NULL");
   if (!std::isfinite(kappa) || kappa <= 0) return fail(WD_EINVAL, "kappa must be finite and > 0");
   if (!(prm->tol > 0) || !std::isfinite(prm->tol)) return fail(WD_EINVAL, "tol must be finite and > 0");
@@ -264,6 +272,10 @@ wd_status validate(int kind, const wd_gauge* g, double kappa, const void* x, con
   if (prm->inner < WD_FP64 || prm->inner > WD_HALF_F16) return fail(WD_EINVAL, "unknown inner precision");
   if (prm->x0_given != 0) return fail(WD_EUNSUPPORTED, "x0_given is not supported");
   if (prm->check_every < 0 || prm->check_every > 1) return fail(WD_EINVAL, "check_every must be 0 or 1");
+  if (prm->restart < 0 || prm->restart > 1) return fail(WD_EINVAL, "restart must be 0 or 1");
+  if (prm->restart == 1 && !(prm->delta > 0.0))
+    return fail(WD_EINVAL, "defect correction needs an inner tolerance delta > 0");
+  if (!g) return fail(WD_EINVAL, "gauge handle is NULL");
   if (!(g->mask & WD_PREC_MASK(WD_FP64)) || !(g->mask & WD_PREC_MASK(prm->inner)))
     return fail(WD_EINVAL, "gauge handle must hold FP64 and the inner precision");
   for (const void* p : {x, b, ws}) {

@@ -1,6 +1,6 @@
 // Autotuner for the dslash launch shape: right-hand sides per thread (nr),
-// RHS-group order in an XCD's sweep (gslow) and the cache policy of the link
-// loads (link_nt).
+// y-sub-slabs of an XCD's sweep (nsub, shortens the reuse distance of the
+// t-neighbours) and the cache policy of the link loads (link_nt).
 //
 // The first eager launch for a (lattice, precision, nrhs) times each
 // candidate with HIP events on the caller's stream, using the plain
@@ -8,10 +8,12 @@
 // Launches made while the stream is being captured into a graph, or whose
 // output aliases their xpay source, use the default shape instead and do not
 // tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
-// across processes (one "Lx Ly Lz Lt prec nrhs nr block gslow nsub link_nt"
-// line per entry); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
-// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt]" forces a shape (y-sub-slabs,
-// nsub, are not searched: they did not pay on the lattices measured).
+// across processes (one "Lx Ly Lz Lt prec nrhs flags nr block gslow nsub
+// link_nt" line per entry, flags = 1 for 8-real links + 2 for temporal
+// gauge); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
+// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs]]]" forces a shape
+// (the RHS-group-slowest order, streaming output stores and the occupancy
+// cap are not searched: none paid on the lattices measured).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -27,7 +29,7 @@ namespace wd {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int>;  // dims, prec, nrhs
+using Key = std::tuple<int, int, int, int, int, int>;  // dims, prec, nrhs, link flags
 
 std::mutex g_mu;
 std::map<Key, LaunchCfg> g_cache;
@@ -35,14 +37,11 @@ bool g_loaded = false;
 
 Key key_of(const wd_gauge* g, wd_prec prec, int nrhs) {
   const Geom& geo = g->geom;
-  return Key{geo.L[0], geo.L[1], geo.L[2], geo.L[3] * 8 + static_cast<int>(prec), nrhs, 0};
+  return Key{geo.L[0], geo.L[1], geo.L[2], geo.L[3] * 8 + static_cast<int>(prec), nrhs,
+             (g->recon == 8 ? 1 : 0) | (g->tgauge ? 2 : 0)};
 }
 
-LaunchCfg default_cfg(wd_prec prec, int nrhs) {
-  int nr = 1;
-  if (nrhs > 1) nr = (prec == WD_FP64) ? 1 : 2;
-  return LaunchCfg{nr, 256};
-}
+LaunchCfg default_cfg(wd_prec, int) { return LaunchCfg{2, 256}; }
 
 const char* cache_path() {
   const char* p = std::getenv("WD_TUNE_CACHE");
@@ -56,12 +55,12 @@ void load_cache_locked() {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  int lx, ly, lz, lt, prec, nrhs, nr, block, gslow, nsub, nt;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &nr, &block,
-                     &gslow, &nsub, &nt) == 11) {
+  int lx, ly, lz, lt, prec, nrhs, flags, nr, block, gslow, nsub, nt;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &flags, &nr,
+                     &block, &gslow, &nsub, &nt) == 12) {
     if (nr >= 1 && nr <= 4 && block == 256 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
         (nt == 0 || nt == 1))
-      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, 0}] = LaunchCfg{nr, block, gslow, nsub, nt};
+      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, flags}] = LaunchCfg{nr, block, gslow, nsub, nt};
   }
   std::fclose(f);
 }
@@ -71,9 +70,9 @@ void save_entry_locked(const Key& k, const LaunchCfg& c) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-               std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), c.nr, c.block, c.gslow, c.nsub,
-               c.link_nt);
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), std::get<5>(k), c.nr, c.block, c.gslow,
+               c.nsub, c.link_nt);
   std::fclose(f);
 }
 
@@ -97,7 +96,7 @@ float time_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& plain, const L
     return -1.0f;
   }
   launch_dslash_cfg(g, prec, plain, c, s);  // warm-up
-  const int reps = 3;
+  const int reps = 2;
   (void)hipEventRecord(e0, s);
   for (int i = 0; i < reps; ++i) launch_dslash_cfg(g, prec, plain, c, s);
   (void)hipEventRecord(e1, s);
@@ -119,22 +118,25 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
   plain.y = nullptr;
   LaunchCfg best = default_cfg(prec, d.out.nrhs);
   float best_ms = -1.0f;
-  // nr = 2 is also tried for a single RHS (its second slot stays empty): the
-  // per-slot branch changes how the compiler schedules the gathers.
-  for (int nr = 1; nr <= 4; ++nr) {
+  // Kernels carry 2..4 RHS slots per thread (a single RHS runs in a
+  // two-slot thread with the second slot empty).
+  const bool slab = g->geom.L[2] % 8 == 0;
+  for (int nr = 2; nr <= 4; ++nr) {
     if (nr > std::max(d.out.nrhs, 2)) break;
-    const int groups = (d.out.nrhs + nr - 1) / nr;
-    for (int gslow = 0; gslow <= (groups > 1 ? 1 : 0); ++gslow) {
+    if (g->recon == 8 && nr > 2) break;  // 8-real kernels exist for two slots
+    for (int nsub = 1; nsub <= (slab ? 4 : 1); nsub *= 2) {
+      if (g->geom.L[1] % nsub) continue;
       for (int nt = 0; nt <= 1; ++nt) {
-        const LaunchCfg c{nr, 256, gslow, 1, nt};
+        const int gslow = 0;
+        const LaunchCfg c{nr, 256, gslow, nsub, nt};
         // the better of two timings, so a clock ramp-up does not decide
         float ms = time_cfg(g, prec, plain, c, s);
         const float ms2 = time_cfg(g, prec, plain, c, s);
         if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
         if (verbose())
-          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: nr %d gslow %d link_nt %d -> %.1f us\n",
+          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: nr %d nsub %d link_nt %d -> %.1f us\n",
                        g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs,
-                       nr, gslow, nt, ms * 1e3f);
+                       nr, nsub, nt, ms * 1e3f);
         if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
           best_ms = ms;
           best = c;

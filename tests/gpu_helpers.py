@@ -10,13 +10,14 @@ DEV = torch.device("cuda:0")
 
 
 class Setup:
-    def __init__(self, dims, U, tap=True, precs=("fp64", "fp32", "i16", "f16")):
+    def __init__(self, dims, U, tap=True, precs=("fp64", "fp32", "i16", "f16"), recon=12, temporal=False):
         self.dims = tuple(dims)
         self.V = int(np.prod(dims))
         self.Vh = self.V // 2
         self.lat = wd.lattice(dims, tap)
         self.U = U
-        self.gauge = wd.Gauge(self.lat, torch.from_numpy(np.ascontiguousarray(U)).to(DEV), precs)
+        self.gauge = wd.Gauge(self.lat, torch.from_numpy(np.ascontiguousarray(U)).to(DEV), precs, recon=recon,
+                              temporal=temporal)
 
     def field(self, prec, nrhs=1):
         return wd.new_field(self.lat, prec, nrhs)

@@ -58,3 +58,22 @@ def test_validation_rejects_bad_lattices_and_arguments(lib):
     bad = wd.lattice((4, 4, 4, 5))
     st = lib.wd_spinor_encode(ctypes.byref(bad), 0, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
     assert st == -1 and b"even" in lib.wd_last_error()
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("restart", 2, b"restart"), ("delta", 1.0, b"delta"), ("nrhs", 0, b"nrhs"), ("tol", 0.0, b"tol"),
+    ("maxiter", 0, b"maxiter"), ("x0_given", 1, b"x0_given")])
+def test_solver_parameters_are_validated_before_any_launch(lib, field, value, msg):
+    import paper_0911_3191_amd as wd
+    p = wd.solve_params(tol=1e-12, inner="f16", delta=0.1, nrhs=1)
+    setattr(p, field, value)
+    st = lib.bicgstab_solve(None, 0.12, None, None, ctypes.byref(p), None, None, 0, None)
+    assert st in (wd.WD_EINVAL, wd.WD_EUNSUPPORTED)
+    assert msg in lib.wd_last_error()
+
+
+def test_defect_correction_needs_an_inner_tolerance(lib):
+    import paper_0911_3191_amd as wd
+    p = wd.solve_params(tol=1e-12, inner="fp32", delta=0.0, restart=True)
+    st = lib.cg_solve(None, 0.12, None, None, ctypes.byref(p), None, None, 0, None)
+    assert st == wd.WD_EINVAL and b"inner tolerance" in lib.wd_last_error()

@@ -1,0 +1,147 @@
+"""8-real links (Appendix A.2) and the temporal gauge (Section 4.3) on the GPU.
+
+Operators on handles with 8-real links are compared with the oracle on the
+exact links (FP64 1e-13, FP32 1e-6, 16-bit 2e-3, relative L2) and, for the
+16-bit formats, on the links the oracle rebuilds from the same quantised
+8 reals.  The device temporal gauge fixing is compared with the oracle's, a
+temporal-gauge handle must give the oracle's operator on the fixed field,
+and full solves through the rotated system must solve the original one.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import wdinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0911_3191_amd as wd  # noqa: E402
+from gpu_helpers import DEV, Setup, rel_l2  # noqa: E402
+
+TOL = {"fp64": 1e-13, "fp32": 1e-6, "i16": 2e-3, "f16": 2e-3}
+PRECS = ["fp64", "fp32", "i16", "f16"]
+DIMS = [(4, 6, 8, 4), (6, 4, 6, 10)]
+
+
+def quantised_links8(kind, U):
+    """The links the 16-bit 8-real format rebuilds, computed by the oracle."""
+    p = oracle.encode_link8(U)
+    p[..., 6:] /= np.pi
+    q = oracle.decode_link16(kind, oracle.encode_link16(kind, p))
+    q[..., 6:] *= np.pi
+    return oracle.decode_link8(q)
+
+
+@pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_recon8_dslash_matches_oracle(dims, prec, dagger):
+    U = wdinputs.gauge_random(dims, 0.5, 91)
+    s = Setup(dims, U, recon=8)
+    psi = wdinputs.spinor_gaussian(dims, 92)
+    _, po = oracle.split(dims, psi)
+    fin = s.encode_full(prec, psi, 1)
+    fout = s.field(prec)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, dagger, prec)
+    got = s.decode(prec, fout)
+    ref = oracle.dslash_parity(dims, U, po, 0, dagger=bool(dagger))
+    assert rel_l2(got, ref) <= TOL[prec]
+    if prec in ("i16", "f16"):
+        # against the oracle on the same quantised link parameters and spinor
+        q, nm = oracle.encode_spinor16(prec, po)
+        ref_q = oracle.dslash_parity(dims, quantised_links8(prec, U), oracle.decode_spinor16(prec, q, nm), 0,
+                                     dagger=bool(dagger))
+        assert rel_l2(got, ref_q) <= 2e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_recon8_multi_rhs_equals_single_rhs(prec):
+    dims = (4, 6, 8, 4)
+    U = wdinputs.gauge_random(dims, 0.5, 93)
+    s = Setup(dims, U, recon=8)
+    srcs = wdinputs.spinor_gaussian(dims, 94, nrhs=3)
+    fin = s.encode_full(prec, srcs, 1, nrhs=3)
+    fout = s.field(prec, 3)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 3)
+    multi = s.decode(prec, fout, 3)
+    for k in range(3):
+        f1 = s.encode_full(prec, srcs[k], 1)
+        o1 = s.field(prec)
+        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        assert np.array_equal(s.decode(prec, o1), multi[k])
+
+
+def test_device_temporal_gauge_fixing_matches_oracle():
+    dims = (4, 6, 8, 6)
+    U = wdinputs.gauge_random(dims, 0.5, 95)
+    lat = wd.lattice(dims)
+    Ud = torch.from_numpy(U).to(DEV)
+    Uf, g = wd.gauge_fix_temporal(lat, Ud)
+    torch.cuda.synchronize()
+    Uo, go = oracle.gauge_fix_temporal(dims, U)
+    assert np.abs(Uf.cpu().numpy().reshape(Uo.shape) - Uo).max() < 1e-12
+    assert np.abs(g.cpu().numpy().reshape(go.shape) - go).max() < 1e-12
+    psi = wdinputs.spinor_gaussian(dims, 96, nrhs=2)
+    pd = torch.from_numpy(psi).to(DEV)
+    out = torch.empty_like(pd)
+    wd.wd_gauge_rotate_spinor(lat, g, out, pd, 2)
+    torch.cuda.synchronize()
+    ref = oracle.gauge_rotate_spinor(dims, go, psi)
+    assert np.abs(out.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-13
+    wd.wd_gauge_rotate_spinor(lat, g, out, out, 2, adjoint=True)
+    torch.cuda.synchronize()
+    assert np.abs(out.cpu().numpy().reshape(psi.shape) - psi).max() < 1e-13
+
+
+def test_temporal_handle_refuses_a_field_not_in_temporal_gauge():
+    dims = (4, 4, 4, 4)
+    U = wdinputs.gauge_random(dims, 0.3, 97)
+    with pytest.raises(wd.WDError) as e:
+        Setup(dims, U, temporal=True)
+    assert e.value.status == wd.WD_EINVAL and "temporal gauge" in str(e.value)
+
+
+@pytest.mark.parametrize("recon", [12, 8])
+@pytest.mark.parametrize("prec", PRECS)
+def test_temporal_gauge_dslash_matches_oracle_on_the_fixed_field(recon, prec):
+    dims = (6, 4, 8, 6)
+    U = wdinputs.gauge_random(dims, 0.5, 98)
+    Uf, _ = oracle.gauge_fix_temporal(dims, U)
+    s = Setup(dims, Uf, recon=recon, temporal=True)
+    psi = wdinputs.spinor_gaussian(dims, 99)
+    _, po = oracle.split(dims, psi)
+    for dagger in (0, 1):
+        fin = s.encode_full(prec, psi, 1)
+        fout = s.field(prec)
+        wd.wilson_dslash(s.gauge, fout, fin, 0, dagger, prec)
+        ref = oracle.dslash_parity(dims, Uf, po, 0, dagger=bool(dagger))
+        assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec], dagger
+
+
+@pytest.mark.parametrize("inner,recon", [("fp32", 8), ("f16", 12), ("f16", 8)])
+def test_solve_in_temporal_gauge_solves_the_original_system(inner, recon):
+    """Fix the gauge on the device, solve with G b on a temporal-gauge handle
+    (8- or 12-real links), rotate back: the oracle's true residual of the
+    original system is below 1e-12."""
+    dims, kappa = (6, 4, 8, 6), 0.124
+    U = wdinputs.gauge_random(dims, 0.3, 100)
+    lat = wd.lattice(dims)
+    Uf, g = wd.gauge_fix_temporal(lat, torch.from_numpy(U).to(DEV))
+    gauge = wd.Gauge(lat, Uf, ("fp64", inner), recon=recon, temporal=True)
+    b = wdinputs.spinor_gaussian(dims, 101)
+    bd = torch.from_numpy(b).to(DEV).reshape(1, -1)
+    bg = torch.empty_like(bd)
+    wd.wd_gauge_rotate_spinor(lat, g, bg, bd, 1)
+    p = wd.solve_params(tol=1e-12, maxiter=5000, inner=inner, delta=0.1)
+    ws = wd.new_workspace(lat, p, "bicgstab")
+    x = torch.zeros_like(bg)
+    st, info = wd.bicgstab_solve(gauge, kappa, x, bg, p, ws)
+    assert st == wd.WD_OK, info
+    wd.wd_gauge_rotate_spinor(lat, g, x, x, 1, adjoint=True)
+    torch.cuda.synchronize()
+    rr = oracle.true_relres(dims, U, kappa, b, x.cpu().numpy().reshape(b.shape))
+    assert rr <= 1e-12, (rr, info)

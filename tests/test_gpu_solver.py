@@ -163,3 +163,39 @@ def test_config3_cg_twelve_point_sources_graph():
         for k in (0, 5, 11):
             rr = oracle.true_relres(dims, U, kappa, b[k], x[k])
             assert rr <= 1e-12, f"{inner} rhs {k}: {rr:.3e}"
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "cg"])
+@pytest.mark.parametrize("inner,eps_in", [("fp32", 1e-4), ("f16", 1e-2), ("f16", 0.1)])
+def test_defect_correction_solves_reach_1e12(solver, inner, eps_in):
+    """Algorithm 1: inner solves to eps_in relative to the residual they start
+    from, each restarted from the FP64 residual, until the true residual is
+    below 1e-12."""
+    dims, kappa = (6, 4, 6, 10), 0.124
+    U = wdinputs.gauge_random(dims, 0.3, 7)
+    s = Setup(dims, U, precs=("fp64", inner))
+    b = wdinputs.spinor_gaussian(dims, 8)
+    st, x, info = run(s, solver, b, kappa, tol=1e-12, inner=inner, delta=eps_in, maxiter=5000, restart=True)
+    assert st == wd.WD_OK, info
+    rr = oracle.true_relres(dims, U, kappa, b, x)
+    assert rr <= 1e-12, f"{solver}/{inner}: oracle true residual {rr:.3e}, info {info}"
+    assert info["reliable_updates"] >= 2  # outer corrections
+
+
+def test_config2_defect_correction_against_reliable_updates():
+    """24^3x32, eps 0.3 seed 2, kappa 0.124: both mixed schemes reach 1e-12
+    (the iteration counts are printed; the benchmark reports the comparison)."""
+    dims, kappa = (24, 24, 24, 32), 0.124
+    U = wdinputs.gauge_random(dims, 0.3, 2)
+    s = Setup(dims, U, precs=("fp64", "fp32", "f16"))
+    b = wdinputs.spinor_gaussian(dims, 1002)
+    res = {}
+    for inner in ("fp32", "f16"):
+        st, x, ru = run(s, "bicgstab", b, kappa, tol=1e-12, inner=inner, delta=0.1, maxiter=20000,
+                        use_graph=True)
+        assert st == wd.WD_OK and oracle.true_relres(dims, U, kappa, b, x) <= 1e-12
+        st, x, dc = run(s, "bicgstab", b, kappa, tol=1e-12, inner=inner, delta=0.1, maxiter=20000,
+                        use_graph=True, restart=True)
+        assert st == wd.WD_OK and oracle.true_relres(dims, U, kappa, b, x) <= 1e-12
+        res[inner] = (ru["iters"], dc["iters"])
+    print("config2 iterations (reliable updates, defect correction):", res)
