@@ -16,7 +16,9 @@ Reported:
                    by the step's wall time)
   roofline         the dominant kernel (12-RHS binary16 dslash): algorithmic
                    bytes per launch / average launch time (HIP events on its
-                   stream), against 8 TB/s
+                   stream), against 8 TB/s; traffic = HBM-side bytes per launch
+                   (FETCH_SIZE + WRITE_SIZE from the committed counter summary,
+                   when it was taken on the current kernel source)
   time_to_solution mixed 12-RHS batch vs the plain FP64 single-RHS BiCGstab
   cpu_baseline     the FP64 oracle on a bounded sample (see --help)
 """
@@ -372,13 +374,13 @@ def main():
                    "lattice": args.dims, "kappa": KAPPA, "eps": EPS, "seed": SEED, "nrhs": NRHS,
                    "sources": "12 spin-colour point sources at the origin", "inner": inner,
                    "delta": 0.1, "recon": 12, "graph": True, "arith": "f32 inner, f64 reductions/updates"},
-        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": f"dslash_kernel<{inner}> {NRHS}-RHS",
-                     "flops_per_launch": dflops, "bytes_per_launch": dbytes,
-                     "us_per_launch": round(t_dslash * 1e6, 1),
-                     "hbm_achieved_GBps": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
+                     "bytes_per_launch": dbytes, "us_per_launch": round(t_dslash * 1e6, 1),
+                     "flops_per_launch": dflops, "alu_achieved_TFLOPs": round(tflops, 2),
+                     "alu_frac": round(tflops / ALU_PEAK_TFLOPS, 4)},
         "time_to_solution": {"mixed_batch_s": round(ms_per_step * 1e-3, 3),
                              "mixed_per_rhs_s": round(per_rhs_mixed, 4),
                              "fp64_single_rhs_s": round(fp64["seconds"], 3) if fp64 else None,
