@@ -242,7 +242,23 @@ def main():
         fp64 = {"seconds": t64, "iters": inf64[0]["iters"], "true_rel_resid": inf64[0]["true_rel_resid"],
                 "status": st64}
         log(f"fp64 reference: {t64:.3f}s iters {inf64[0]['iters']}")
-        del ws64, b0, x0
+        del ws64
+        # the same single source by the mixed solver (warmed once, then timed)
+        p1 = wd.solve_params(tol=1e-12, maxiter=20000, inner=inner, delta=0.1, nrhs=1, use_graph=True)
+        ws1 = wd.new_workspace(lat, p1, "bicgstab")
+        with torch.cuda.stream(stream):
+            wd.bicgstab_solve(gauge, KAPPA, x0, b0, p1, ws1, stream)
+        x0.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            st1, inf1 = wd.bicgstab_solve(gauge, KAPPA, x0, b0, p1, ws1, stream)
+        torch.cuda.synchronize()
+        fp64["mixed_single_rhs"] = {"seconds": time.perf_counter() - t1, "iters": inf1[0]["iters"],
+                                    "reliable_updates": inf1[0]["reliable_updates"],
+                                    "true_rel_resid": inf1[0]["true_rel_resid"], "status": st1}
+        log(f"mixed single RHS: {fp64['mixed_single_rhs']}")
+        del ws1, b0, x0
         torch.cuda.empty_cache()
 
     # ---- dominant kernel: 12-RHS dslash in the inner precision, HIP events on its stream ----
@@ -389,6 +405,10 @@ def main():
                              "iters_fp64": fp64["iters"] if fp64 else None,
                              "true_rel_resid_max": worst_res,
                              "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None,
+                             "mixed_single_rhs_s": (round(fp64["mixed_single_rhs"]["seconds"], 3)
+                                                    if fp64 else None),
+                             "speedup_single_rhs": (round(fp64["seconds"] / fp64["mixed_single_rhs"]["seconds"], 2)
+                                                    if fp64 else None),
                              "defect_correction": dc},
         "dslash_single_rhs": table,
         "copy_GBps": round(copy_gbs, 1),
