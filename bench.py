@@ -86,7 +86,7 @@ def prepare_bytes(nrhs: int) -> int:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in ("wd_dslash.hip", "wd_device.h", "wd_reduce.h"):
+    for name in ("wd_dslash_impl.h", "wd_dslash.hip", "wd_device.h", "wd_reduce.h"):
         with open(os.path.join(ROOT, "paper_0911_3191_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

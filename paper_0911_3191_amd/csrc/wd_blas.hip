@@ -267,32 +267,6 @@ __global__ void __launch_bounds__(kBlock) k_scale_bnorm(int Vh, FieldView f, con
   store_spinor<SF64>(f, rhs, i, a);
 }
 
-// r (FP64) <- b - r; partials: |r|^2 (FP64).  r holds M_hat x on entry.
-__global__ void __launch_bounds__(kBlock) k_residual(int Vh, FieldView r, FieldView b,
-                                                     const int* __restrict__ mask,
-                                                     double* __restrict__ partials) {
-  const int rhs = blockIdx.y;
-  if (mask && !mask[rhs]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double d[1] = {0.0};
-  if (i < Vh) {
-    Spinor<double> Rr, B;
-    load_spinor<SF64>(r, rhs, i, Rr);
-    load_spinor<SF64>(b, rhs, i, B);
-    double nn = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        Rr.v[s][c] = B.v[s][c] - Rr.v[s][c];
-        nn += Rr.v[s][c].re * Rr.v[s][c].re + Rr.v[s][c].im * Rr.v[s][c].im;
-      }
-    store_spinor<SF64>(r, rhs, i, Rr);
-    d[0] = nn;
-  }
-  block_sum_store<1>(d, partials + ((int64_t)rhs * gridDim.x + blockIdx.x) * kMaxDot);
-}
-
 // rh <- enc(r64); xh <- 0; partials: |rh|^2, <rt, rh> (rt may be null).
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_reencode(int Vh, FieldView rh, FieldView xh, FieldView r64,
@@ -591,12 +565,6 @@ hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int*
 
 hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s) {
   k_scale_bnorm<<<grid_of(g, f64.nrhs), kBlock, 0, s>>>(g.Vh, fv(f64), sc, down);
-  return hipGetLastError();
-}
-
-hipError_t blas_residual(const Geom& g, Field r64, Field b64, const int* mask, double* partials,
-                         hipStream_t s) {
-  k_residual<<<grid_of(g, r64.nrhs), kBlock, 0, s>>>(g.Vh, fv(r64), fv(b64), mask, partials);
   return hipGetLastError();
 }
 

@@ -1,782 +1,27 @@
-// Wilson-Dirac hopping term on one parity (Section 3, Eq. 1), for the
-// storage formats FP64, FP32, int16 + norm and binary16 + norm.
-//
-// One thread computes one output site of parity p for NR right-hand sides:
-// for each direction mu it loads and rebuilds the link once (12 reals ->
-// 3x3, Appendix A.1), then for each of its RHS gathers the neighbour of the
-// opposite parity, projects it onto its rank-2 spin subspace (6 complex
-// numbers), multiplies by U (forward) or U^dagger (backward), expands back to
-// 4 spins and accumulates.  The t-boundary sign is applied to the hop, never
-// folded into the stored link.
-//
-// Spin projection in the DeGrand-Rossi basis (Appendix B): every gamma_mu is
-// off-diagonal in 2x2 blocks, gamma_mu = [[0, A_mu], [A_mu^dag, 0]], so
-//   (1 + s gamma_mu) psi = [ h ; s A_mu^dag h ],  h = psi_up + s A_mu psi_down,
-// with s = -1 on the forward hop and s = +1 on the backward hop of D (the
-// adjoint swaps them).  Each A_mu has one entry per row, a power of i:
-//   A_x = [[0, i], [i, 0]],  A_y = [[0, -1], [1, 0]],
-//   A_z = [[i, 0], [0, -i]], A_t = [[1, 0], [0, 1]].
-//
-// 16-bit neighbours are projected and multiplied in units of their own site
-// norm; the norm enters once, in the accumulating FMA.
-//
-// Work distribution (XCD-aware): the 8 XCDs of the chip each own one z-slab
-// of the lattice and sweep it with t slowest, so the two t-neighbour slices a
-// site needs were fetched by the same XCD shortly before (its own L2 holds
-// them for single-RHS FP32/FP64).  Hardware assigns workgroup b to XCD b % 8;
-// within an XCD, consecutive workgroups take consecutive slab positions, and
-// the RHS groups of one site block are adjacent so their link loads hit L2.
-// Lattices with Lz not divisible by 8 fall back to one contiguous
-// checkerboard range per XCD.
-#include "wd_device.h"
-#include "wd_reduce.h"
+// Dslash entry points: dispatch to the per-format launchers, tuned launch
+// shapes, partial-record counts (kernels: wd_dslash_impl.h).
+#include "wd_dslash_impl.h"
 
 namespace wd {
 
-// Row k of A_mu has its entry in column P_k with value i^PH_k.
-template <int MU>
-struct Gamma;
-template <> struct Gamma<0> { static constexpr int P0 = 1, P1 = 0, PH0 = 1, PH1 = 1; };
-template <> struct Gamma<1> { static constexpr int P0 = 1, P1 = 0, PH0 = 2, PH1 = 0; };
-template <> struct Gamma<2> { static constexpr int P0 = 0, P1 = 1, PH0 = 1, PH1 = 3; };
-template <> struct Gamma<3> { static constexpr int P0 = 0, P1 = 1, PH0 = 0, PH1 = 0; };
-
-// n / d for n < 2^31 with a precomputed multiplier (round-up method).
-struct FastDiv {
-  uint32_t m, s;
-};
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
-  return (__umulhi(n, f.m) + n) >> f.s;
-}
-static FastDiv make_fastdiv(uint32_t d) {
-  uint32_t s = 0;
-  while ((1ull << s) < d) ++s;
-  const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1;
-  return FastDiv{static_cast<uint32_t>(m), s};
-}
-
-struct DslashGeom {
-  int L[4];
-  int Lxh, Vh, tap;
-  int64_t stride;       // chunk stride of every field and of the links
-  FastDiv div_lxh;      // / Lxh
-  FastDiv div_ly;       // / Ly
-  FastDiv div_lz;       // / Lz
-  int slab;             // 1: z-slab mapping, 0: contiguous range per XCD
-  int nsub;             // y-sub-slabs per XCD slab, swept one after the other
-  int sub_sites;        // sites of one parity in one sub-slab (all t)
-  int sub_t_sites;      // ... at fixed t: Lxh * (Ly / nsub) * (Lz / 8)
-  int sub_plane;        // Lxh * (Ly / nsub)
-  FastDiv div_sub;      // / sub_sites
-  FastDiv div_sub_t;    // / sub_t_sites
-  FastDiv div_sub_plane;  // / sub_plane
-  int site_blocks;      // site blocks per XCD (slab) or in total (contiguous)
-  int ngroups;          // RHS groups
-  int nrhs;
-  int gslow;            // 1: an XCD sweeps its slab once per RHS group (group slowest)
-  int link_nt;          // 1: link loads are marked streaming (read once per launch)
-  int out_nt;           // 1: output stores are marked streaming
-  int tgauge;           // 1: temporal links are the unit matrix off the last time slice
-};
-
-// ---- buffer loads --------------------------------------------------------------
-// Gathers use raw buffer loads: a per-RHS descriptor (base in SGPRs), the
-// site offset as a 32-bit VGPR and the chunk offset as an SGPR, which keeps
-// 64-bit address arithmetic out of the hot loop.  Out-of-range offsets read
-// zero instead of faulting.
-constexpr int kBufWord3 = 0x00020000;  // raw, untyped buffer (gfx9 family)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
-}
-
-template <class S>
-struct SpinorBuf {
-  __amdgpu_buffer_rsrc_t chunks;  // [chunk][site] of one RHS
-  __amdgpu_buffer_rsrc_t norms;   // [site] of one RHS (16-bit formats)
-  uint32_t chunk_bytes;           // stride * 16
-};
-
-template <class S>
-__device__ __forceinline__ SpinorBuf<S> spinor_buf(const FieldView& f, int r) {
-  SpinorBuf<S> b;
-  b.chunk_bytes = (uint32_t)(f.stride * 16);
-  b.chunks = make_rsrc(chunk_base<S>(f, r, 0), b.chunk_bytes * S::NCH);
-  if constexpr (kHalf<S>) b.norms = make_rsrc(norm_base(f, r), (uint32_t)(f.stride * 4));
-  else b.norms = b.chunks;
-  return b;
-}
-
-// AUX is the load's cache policy: 0 default, kStream (nt) marks data read
-// once so that it is evicted first and neighbour spinors stay in L2.
-constexpr int kStream = 2;
-template <int AUX = 0>
-__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
-}
-template <int AUX = 0>
-__device__ __forceinline__ uint2 bload8(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
-}
-
-// Neighbour spinor of one RHS (FP64 / FP32 storage).
-template <class S>
-__device__ __forceinline__ void gather_spinor(const SpinorBuf<S>& b, int i, Spinor<typename S::real>& s) {
-  const uint32_t vo = (uint32_t)i * 16u;
-  if constexpr (S::prec == WD_FP64) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const double2 c = __builtin_bit_cast(double2, bload16(b.chunks, vo, k * b.chunk_bytes));
-      s.v[k / 3][k % 3] = {c.x, c.y};
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float4 c = __builtin_bit_cast(float4, bload16(b.chunks, vo, k * b.chunk_bytes));
-      s.v[(2 * k) / 3][(2 * k) % 3] = {c.x, c.y};
-      s.v[(2 * k + 1) / 3][(2 * k + 1) % 3] = {c.z, c.w};
-    }
-  }
-}
-
-// Neighbour spinor of one RHS in a 16-bit format, left packed: word n holds
-// complex component n = 3 spin + colour as (re | im << 16).  scale = the
-// factor that turns stored values into reals (norm, or norm / 32767).
-struct Raw16 {
-  uint32_t w[12];
-};
-template <class S>
-__device__ __forceinline__ void gather_spinor16(const SpinorBuf<S>& b, int i, Raw16& s, float& scale) {
-  const uint32_t vo = (uint32_t)i * 16u;
-  const float nm = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.norms, (uint32_t)i * 4u, 0, 0));
-  scale = (S::prec == WD_HALF_I16) ? nm * (1.0f / 32767.0f) : nm;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const uint4 c = bload16(b.chunks, vo, k * b.chunk_bytes);
-    s.w[4 * k] = c.x;
-    s.w[4 * k + 1] = c.y;
-    s.w[4 * k + 2] = c.z;
-    s.w[4 * k + 3] = c.w;
-  }
-}
-
-// Halves of a packed word as binary32 (exact).
-__device__ __forceinline__ float half_lo(uint32_t w) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-}
-__device__ __forceinline__ float half_hi(uint32_t w) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
-}
-
-// a + i^N b for two packed components, result in binary32.  Binary16: each
-// real is one mixed-precision FMA b * one + a on the stored halves (`one` is
-// 1.0 kept opaque so the multiply is not folded away); both halves convert
-// exactly, so this equals the binary32 sum of the decoded values.  int16: the
-// sum is formed exactly in integers and converted once.
-template <int N, class S>
-__device__ __forceinline__ cx<float> proj16(uint32_t a, uint32_t b, float one) {
-  constexpr int n = ((N % 4) + 4) % 4;
-  if constexpr (S::prec == WD_HALF_F16) {
-    const float ar = half_lo(a), ai = half_hi(a), br = half_lo(b), bi = half_hi(b);
-    if constexpr (n == 0) return {__builtin_fmaf(br, one, ar), __builtin_fmaf(bi, one, ai)};
-    else if constexpr (n == 1) return {__builtin_fmaf(-bi, one, ar), __builtin_fmaf(br, one, ai)};
-    else if constexpr (n == 2) return {__builtin_fmaf(-br, one, ar), __builtin_fmaf(-bi, one, ai)};
-    else return {__builtin_fmaf(bi, one, ar), __builtin_fmaf(-br, one, ai)};
-  } else {
-    const int ar = (int16_t)(a & 0xffffu), ai = (int16_t)(a >> 16);
-    const int br = (int16_t)(b & 0xffffu), bi = (int16_t)(b >> 16);
-    if constexpr (n == 0) return {(float)(ar + br), (float)(ai + bi)};
-    else if constexpr (n == 1) return {(float)(ar - bi), (float)(ai + br)};
-    else if constexpr (n == 2) return {(float)(ar - br), (float)(ai - bi)};
-    else return {(float)(ar + bi), (float)(ai - br)};
-  }
-}
-
-// Rows a, b of link (par, mu) at site i, third row rebuilt as (a x b)^*.
-template <class S, int AUX>
-__device__ __forceinline__ void gather_link_aux(const char* links, int64_t stride, int par, int mu, int i,
-                                                Link<typename S::real>& L) {
-  using R = typename S::real;
-  constexpr int N = LinkChunks<S>::N, B = LinkChunks<S>::BYTES;
-  const uint32_t cbytes = (uint32_t)(stride * B);
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(link_chunk<S>(links, stride, par, mu, 0), cbytes * N);
-  const uint32_t vo = (uint32_t)i * (uint32_t)B;
-  cx<R> e[6];
-  if constexpr (S::prec == WD_FP64) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const double2 c = __builtin_bit_cast(double2, bload16<AUX>(rs, vo, k * cbytes));
-      e[k] = {c.x, c.y};
-    }
-  } else if constexpr (S::prec == WD_FP32) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float4 c = __builtin_bit_cast(float4, bload16<AUX>(rs, vo, k * cbytes));
-      e[2 * k] = {c.x, c.y};
-      e[2 * k + 1] = {c.z, c.w};
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint2 c = bload8<AUX>(rs, vo, k * cbytes);
-      const uint32_t w[2] = {c.x, c.y};
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const uint16_t lo = (uint16_t)(w[j] & 0xffffu), hi = (uint16_t)(w[j] >> 16);
-        if constexpr (S::prec == WD_HALF_I16)
-          e[2 * k + j] = {(float)(int16_t)lo * (1.0f / 32767.0f), (float)(int16_t)hi * (1.0f / 32767.0f)};
-        else
-          e[2 * k + j] = {h16_to_f(lo), h16_to_f(hi)};
-      }
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    L.u[0][b] = e[b];
-    L.u[1][b] = e[3 + b];
-  }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-    L.u[2][j] = conj(L.u[0][j1] * L.u[1][j2] - L.u[0][j2] * L.u[1][j1]);
-  }
-}
-
-__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
-
-// Link of (par, mu) at site i stored as 8 reals (Appendix A.2): a2, a3, b1 and
-// the phases of a1 and c1 (16-bit formats: phases / pi).  Rebuilt with
-// |a1| = sqrt(1 - |a2|^2 - |a3|^2), |c1| = sqrt(1 - |a1|^2 - |b1|^2) (negative
-// arguments taken as zero), N = sqrt(|a2|^2 + |a3|^2), the plane vectors
-// b' = (0, -a3*, a2*) / N and c' = (N, -a1* a2 / N, -a1* a3 / N), and the
-// rotation b = p1 b' + p2 c', c = -p2* b' + p1* c' with p1 = c1* / N,
-// p2 = b1 / N.
-template <class S, int AUX>
-__device__ __forceinline__ void gather_link8(const char* links, int64_t stride, int par, int mu, int i,
-                                          Link<typename S::real>& L) {
-  using R = typename S::real;
-  constexpr int N8 = (S::prec == WD_FP64) ? 4 : (S::prec == WD_FP32 ? 2 : 1);  // 16-byte chunks
-  const uint32_t cbytes = (uint32_t)(stride * 16);
-  const __amdgpu_buffer_rsrc_t rs =
-      make_rsrc(links + (int64_t)((par * 4 + mu) * N8) * stride * 16, cbytes * N8);
-  const uint32_t vo = (uint32_t)i * 16u;
-  R v[8];
-  if constexpr (S::prec == WD_FP64) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double2 c = __builtin_bit_cast(double2, bload16<AUX>(rs, vo, k * cbytes));
-      v[2 * k] = c.x;
-      v[2 * k + 1] = c.y;
-    }
-  } else if constexpr (S::prec == WD_FP32) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const float4 c = __builtin_bit_cast(float4, bload16<AUX>(rs, vo, k * cbytes));
-      v[4 * k] = c.x;
-      v[4 * k + 1] = c.y;
-      v[4 * k + 2] = c.z;
-      v[4 * k + 3] = c.w;
-    }
-  } else {
-    const uint4 c = bload16<AUX>(rs, vo, 0);
-    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if constexpr (S::prec == WD_HALF_I16) {
-        v[2 * j] = (float)(int16_t)(w[j] & 0xffffu) * (1.0f / 32767.0f);
-        v[2 * j + 1] = (float)(int16_t)(w[j] >> 16) * (1.0f / 32767.0f);
-      } else {
-        v[2 * j] = half_lo(w[j]);
-        v[2 * j + 1] = half_hi(w[j]);
-      }
-    }
-    v[6] *= 3.14159265358979323846f;
-    v[7] *= 3.14159265358979323846f;
-  }
-  const cx<R> a2 = {v[0], v[1]}, a3 = {v[2], v[3]}, b1 = {v[4], v[5]};
-  const R n2 = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
-  R t = R(1) - n2;
-  const R ma1 = t > R(0) ? sqrt(t) : R(0);
-  t = R(1) - (ma1 * ma1 + (b1.re * b1.re + b1.im * b1.im));
-  const R mc1 = t > R(0) ? sqrt(t) : R(0);
-  R s1, c1c, s2, c2c;
-  sincos_r(v[6], &s1, &c1c);
-  sincos_r(v[7], &s2, &c2c);
-  const cx<R> a1 = {ma1 * c1c, ma1 * s1}, c1 = {mc1 * c2c, mc1 * s2};
-  const R nn = sqrt(n2);
-  const R rn = R(1) / nn;
-  // plane vectors b' (first entry 0) and c'
-  const cx<R> bp1 = {-a3.re * rn, a3.im * rn}, bp2 = {a2.re * rn, -a2.im * rn};
-  const cx<R> a1c = conj(a1);
-  const cx<R> cp1 = (-rn) * (a1c * a2), cp2 = (-rn) * (a1c * a3);
-  const cx<R> p1 = rn * conj(c1), p2 = rn * b1;
-  const cx<R> p1c = conj(p1), p2c = conj(p2);
-  L.u[0][0] = a1;
-  L.u[0][1] = a2;
-  L.u[0][2] = a3;
-  L.u[1][0] = nn * p2;
-  L.u[1][1] = p1 * bp1 + p2 * cp1;
-  L.u[1][2] = p1 * bp2 + p2 * cp2;
-  L.u[2][0] = nn * p1c;
-  L.u[2][1] = p1c * cp1 - p2c * bp1;
-  L.u[2][2] = p1c * cp2 - p2c * bp2;
-}
-
-template <typename R>
-__device__ __forceinline__ void unit_link(Link<R>& L) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) L.u[a][b] = {a == b ? R(1) : R(0), R(0)};
-}
-
-// Link of (par, mu) at site i in the handle's format, with the launch's cache
-// policy for links.
-template <class S, int RECON>
-__device__ __forceinline__ void gather_link(const DslashGeom& g, const char* links, int par, int mu, int i,
-                                            Link<typename S::real>& L) {
-  if constexpr (RECON == 8) {
-    if (g.link_nt) gather_link8<S, kStream>(links, g.stride, par, mu, i, L);
-    else gather_link8<S, 0>(links, g.stride, par, mu, i, L);
-  } else {
-    if (g.link_nt) gather_link_aux<S, kStream>(links, g.stride, par, mu, i, L);
-    else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
-  }
-}
-
-__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
-// acc + a * b and acc + conj(a) * b as four FMAs
-template <typename R>
-__device__ __forceinline__ cx<R> cmac(cx<R> acc, cx<R> a, cx<R> b) {
-  return {fmar(-a.im, b.im, fmar(a.re, b.re, acc.re)), fmar(a.im, b.re, fmar(a.re, b.im, acc.im))};
-}
-template <typename R>
-__device__ __forceinline__ cx<R> cmacc(cx<R> acc, cx<R> a, cx<R> b) {
-  return {fmar(a.im, b.im, fmar(a.re, b.re, acc.re)), fmar(-a.im, b.re, fmar(a.re, b.im, acc.im))};
-}
-
-// Accumulate one hop: acc += scale * (1 + s gamma_mu) (W psi), W = U or U^dagger
-// (scale carries the 16-bit norm and the t-boundary sign).
-// Multiply the projected half spinor h by W = U or U^dagger, expand to four
-// spins and accumulate: acc += scale * (1 + s gamma_mu) (W psi), where scale
-// carries the 16-bit norm and the t-boundary sign.
-template <int MU, int S, bool DAG_LINK, typename R>
-__device__ __forceinline__ void mul_acc(Spinor<R>& acc, const cx<R> (&h)[2][3], const Link<R>& U, R scale) {
-  using G = Gamma<MU>;
-  constexpr int sh = (S < 0) ? 2 : 0;  // multiplying by s = -1 is a factor i^2
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int lo = 2 + (k == 0 ? G::P0 : G::P1);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      cx<R> w = {R(0), R(0)};
-      if constexpr (!DAG_LINK) {
-        w = cmac(w, U.u[a][0], h[k][0]);
-        w = cmac(w, U.u[a][1], h[k][1]);
-        w = cmac(w, U.u[a][2], h[k][2]);
-      } else {
-        w = cmacc(w, U.u[0][a], h[k][0]);
-        w = cmacc(w, U.u[1][a], h[k][1]);
-        w = cmacc(w, U.u[2][a], h[k][2]);
-      }
-      // upper spin k gets w; lower spin P_k gets s conj(A[k][P_k]) w = i^(sh - PH_k) w
-      acc.v[k][a] = acc.v[k][a] + scale * w;
-      const cx<R> wl = (k == 0) ? iph<sh - G::PH0 + 4>(w) : iph<sh - G::PH1 + 4>(w);
-      acc.v[lo][a] = acc.v[lo][a] + scale * wl;
-    }
-  }
-}
-
-// One hop from a decoded neighbour (FP64 / FP32 storage).
-template <int MU, int S, bool DAG_LINK, typename R>
-__device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const Link<R>& U, R scale) {
-  using G = Gamma<MU>;
-  constexpr int sh = (S < 0) ? 2 : 0;
-  cx<R> h[2][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    h[0][c] = psi.v[0][c] + iph<G::PH0 + sh>(psi.v[2 + G::P0][c]);
-    h[1][c] = psi.v[1][c] + iph<G::PH1 + sh>(psi.v[2 + G::P1][c]);
-  }
-  mul_acc<MU, S, DAG_LINK>(acc, h, U, scale);
-}
-
-// One hop from a packed 16-bit neighbour: the projection reads the stored
-// values directly (see proj16), in units of the neighbour's norm.
-template <int MU, int S, bool DAG_LINK, class SF>
-__device__ __forceinline__ void hop16(Spinor<float>& acc, const Raw16& psi, const Link<float>& U, float scale,
-                                      float one) {
-  using G = Gamma<MU>;
-  constexpr int sh = (S < 0) ? 2 : 0;
-  cx<float> h[2][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    h[0][c] = proj16<G::PH0 + sh, SF>(psi.w[c], psi.w[3 * (2 + G::P0) + c], one);
-    h[1][c] = proj16<G::PH1 + sh, SF>(psi.w[3 + c], psi.w[3 * (2 + G::P1) + c], one);
-  }
-  mul_acc<MU, S, DAG_LINK>(acc, h, U, scale);
-}
-
-// Both hops of direction MU for the NR right-hand sides of this thread.
-template <class S, int MU, bool DAGGER, int NR, int RECON>
-__device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
-                                         const char* __restrict__ links, const SpinorBuf<S> (&in)[NR],
-                                         const bool (&on)[NR], int p, int cb, int xh, int row,
-                                         const int (&X)[4], float one) {
-  using R = typename S::real;
-  // neighbour checkerboard indices; row = y + Ly (z + Lz t)
-  int nf, nb;
-  bool flip_f = false, flip_b = false;
-  if constexpr (MU == 0) {
-    const int xf = (X[0] + 1 == g.L[0]) ? 0 : X[0] + 1;
-    const int xb = (X[0] == 0) ? g.L[0] - 1 : X[0] - 1;
-    nf = (xf >> 1) + g.Lxh * row;
-    nb = (xb >> 1) + g.Lxh * row;
-  } else {
-    int step = 1;
-    if constexpr (MU >= 2) step *= g.L[1];
-    if constexpr (MU == 3) step *= g.L[2];
-    const int rf = (X[MU] + 1 == g.L[MU]) ? row - (g.L[MU] - 1) * step : row + step;
-    const int rb = (X[MU] == 0) ? row + (g.L[MU] - 1) * step : row - step;
-    nf = xh + g.Lxh * rf;
-    nb = xh + g.Lxh * rb;
-    if constexpr (MU == 3) {
-      flip_f = g.tap && (X[3] == g.L[3] - 1);
-      flip_b = g.tap && (X[3] == 0);
-    }
-  }
-  // temporal gauge: U_t is the unit matrix off the last time slice, so the
-  // forward t-hop reads a link only from t = Lt - 1, the backward one only
-  // into t = 0 (elsewhere the unit matrix is applied without a load)
-  bool unit_f = false, unit_b = false;
-  if constexpr (MU == 3) {
-    unit_f = g.tgauge && X[3] != g.L[3] - 1;
-    unit_b = g.tgauge && X[3] != 0;
-  }
-  // forward: (1 - gamma_mu) U_x^mu psi(x + mu); adjoint: (1 + gamma_mu)
-  {
-    Link<R> U;
-    if (unit_f) unit_link(U);
-    else gather_link<S, RECON>(g, links, p, MU, cb, U);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      if (!on[k]) continue;
-      if constexpr (kHalf<S>) {
-        Raw16 psi;
-        float sc;
-        gather_spinor16<S>(in[k], nf, psi, sc);
-        if (flip_f) sc = -sc;
-        hop16<MU, DAGGER ? +1 : -1, false, S>(acc[k], psi, U, sc, one);
-      } else {
-        Spinor<R> psi;
-        gather_spinor<S>(in[k], nf, psi);
-        hop<MU, DAGGER ? +1 : -1, false>(acc[k], psi, U, flip_f ? R(-1) : R(1));
-      }
-    }
-  }
-  // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
-  {
-    Link<R> U;
-    if (unit_b) unit_link(U);
-    else gather_link<S, RECON>(g, links, 1 - p, MU, nb, U);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      if (!on[k]) continue;
-      if constexpr (kHalf<S>) {
-        Raw16 psi;
-        float sc;
-        gather_spinor16<S>(in[k], nb, psi, sc);
-        if (flip_b) sc = -sc;
-        hop16<MU, DAGGER ? -1 : +1, true, S>(acc[k], psi, U, sc, one);
-      } else {
-        Spinor<R> psi;
-        gather_spinor<S>(in[k], nb, psi);
-        hop<MU, DAGGER ? -1 : +1, true>(acc[k], psi, U, flip_b ? R(-1) : R(1));
-      }
-    }
-  }
-}
-
-// out = D in, or out = x + a * D in (XPAY), optionally followed by per-block
-// FP64 partial dot products of the result (DOT):
-//   DOT_YO: <y, out>                 (complex; BiCGstab <r~, v>)
-//   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
-//   DOT_OO: |out|^2                  (CG |M p|^2)
-// Right-hand sides whose active flag is 0 are skipped.
-template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON>
-__global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
-                                                       FieldView out, FieldView in, FieldView xs,
-                                                       FieldView ys, typename S::real a, int p,
-                                                       const int* __restrict__ active,
-                                                       double* __restrict__ partials) {
-  using R = typename S::real;
-  // ---- which sites and RHS this workgroup owns ----
-  const int xcd = blockIdx.x & 7;
-  const int j = blockIdx.x >> 3;
-  int site_block, group, pid, cb;
-  int xh = 0, X1 = 0, X2 = 0, X3 = 0;  // site coordinates (x / 2, y, z, t)
-  bool valid;
-  if (g.slab) {
-    if (g.gslow) {
-      group = j / g.site_blocks;
-      site_block = j - group * g.site_blocks;
-    } else {
-      site_block = j / g.ngroups;
-      group = j - site_block * g.ngroups;
-    }
-    if (site_block >= g.site_blocks || group >= g.ngroups) return;
-    pid = xcd * g.site_blocks + site_block;
-    // position in this XCD's slab: sub-slab (slowest), t, z, y, x/2 (fastest)
-    const int s_local = site_block * blockDim.x + threadIdx.x;
-    valid = s_local < (g.Vh >> 3);
-    const int sub = (int)fdiv((uint32_t)s_local, g.div_sub);
-    const int r1 = s_local - sub * g.sub_sites;
-    X3 = (int)fdiv((uint32_t)r1, g.div_sub_t);
-    const int r2 = r1 - X3 * g.sub_t_sites;
-    const int zl = (int)fdiv((uint32_t)r2, g.div_sub_plane);
-    const int r3 = r2 - zl * g.sub_plane;
-    const int yl = (int)fdiv((uint32_t)r3, g.div_lxh);
-    xh = r3 - yl * g.Lxh;
-    X1 = sub * (g.L[1] / g.nsub) + yl;
-    X2 = xcd * (g.L[2] >> 3) + zl;
-    cb = xh + g.Lxh * (X1 + g.L[1] * (X2 + g.L[2] * X3));
-  } else {
-    const int per = (g.site_blocks * g.ngroups + 7) >> 3;
-    const int L = xcd * per + j;
-    if (j >= per || L >= g.site_blocks * g.ngroups) return;
-    site_block = L / g.ngroups;
-    group = L - site_block * g.ngroups;
-    pid = site_block;
-    cb = site_block * blockDim.x + threadIdx.x;
-    valid = cb < g.Vh;
-    const int row = (int)fdiv((uint32_t)cb, g.div_lxh);
-    xh = cb - row * g.Lxh;
-    const int zt = (int)fdiv((uint32_t)row, g.div_ly);
-    X1 = row - zt * g.L[1];
-    X3 = (int)fdiv((uint32_t)zt, g.div_lz);
-    X2 = zt - X3 * g.L[2];
-  }
-  int rhs[NR];
-  bool on[NR];
-  bool any = false;
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    rhs[k] = group * NR + k;
-    on[k] = rhs[k] < g.nrhs && (!active || active[rhs[k]]);
-    any |= on[k];
-  }
-  if (!any) return;
-
-  Spinor<R> acc[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k)
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[k].v[s][c] = {R(0), R(0)};
-  if (valid) {
-    // coordinates of the output site (cb, parity p)
-    const int row = X1 + g.L[1] * (X2 + g.L[2] * X3);
-    const int X[4] = {2 * xh + ((p + X1 + X2 + X3) & 1), X1, X2, X3};
-    const float one = pin_f32(1.0f);  // see proj16
-    SpinorBuf<S> ib[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0);
-    hop_pair<S, 0, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 1, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 2, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-    hop_pair<S, 3, DAGGER, NR, RECON>(acc, g, links, ib, on, p, cb, xh, row, X, one);
-  }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    if (!on[k]) continue;  // uniform across the block
-    Spinor<R> x;
-    if (valid) {
-      if constexpr (XPAY) {
-        load_spinor<S>(xs, rhs[k], cb, x);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[k].v[s][c] = x.v[s][c] + a * acc[k].v[s][c];
-      }
-      if (g.out_nt) store_spinor<S, true>(out, rhs[k], cb, acc[k]);
-      else store_spinor<S>(out, rhs[k], cb, acc[k]);
-    }
-    if constexpr (DOT != DOT_NONE) {
-      const int nb = (g.slab ? 8 : 1) * g.site_blocks;
-      double* part = partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot;
-      if constexpr (DOT == DOT_YO) {
-        double d[2] = {0.0, 0.0};
-        if (valid) {
-          Spinor<R> y;
-          load_spinor<S>(ys, rhs[k], cb, y);
-          R re = 0, im = 0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<R> t = cmulc(y.v[s][c], acc[k].v[s][c]);
-              re += t.re;
-              im += t.im;
-            }
-          d[0] = re;
-          d[1] = im;
-        }
-        block_sum_store<2>(d, part);
-      } else if constexpr (DOT == DOT_OX) {
-        double d[3] = {0.0, 0.0, 0.0};
-        if (valid) {
-          R re = 0, im = 0, nn = 0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<R> t = cmulc(acc[k].v[s][c], x.v[s][c]);
-              re += t.re;
-              im += t.im;
-              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
-            }
-          d[0] = re;
-          d[1] = im;
-          d[2] = nn;
-        }
-        block_sum_store<3>(d, part);
-      } else {
-        double d[1] = {0.0};
-        if (valid) {
-          R nn = 0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
-          d[0] = nn;
-        }
-        block_sum_store<1>(d, part);
-      }
-    }
-  }
-}
-
-// ---- launch configuration ---------------------------------------------------------
-static DslashGeom make_dgeom(const Geom& geo, int nrhs, const LaunchCfg& c) {
-  DslashGeom g;
-  for (int m = 0; m < 4; ++m) g.L[m] = geo.L[m];
-  g.Lxh = geo.Lxh;
-  g.Vh = geo.Vh;
-  g.tap = geo.tap;
-  g.stride = geo.stride;
-  g.div_lxh = make_fastdiv(geo.Lxh);
-  g.div_ly = make_fastdiv(geo.L[1]);
-  g.div_lz = make_fastdiv(geo.L[2]);
-  g.nrhs = nrhs;
-  g.ngroups = (nrhs + c.nr - 1) / c.nr;
-  g.gslow = c.gslow;
-  g.link_nt = c.link_nt;
-  g.out_nt = c.out_nt;
-  g.tgauge = 0;
-  g.slab = (geo.L[2] % 8 == 0) ? 1 : 0;
-  g.nsub = (c.nsub >= 1 && geo.L[1] % c.nsub == 0) ? c.nsub : 1;
-  g.sub_plane = geo.Lxh * (geo.L[1] / g.nsub);
-  g.sub_t_sites = g.sub_plane * (geo.L[2] / 8);
-  g.sub_sites = g.sub_t_sites * geo.L[3];
-  g.div_sub = make_fastdiv(g.sub_sites > 0 ? g.sub_sites : 1);
-  g.div_sub_t = make_fastdiv(g.sub_t_sites > 0 ? g.sub_t_sites : 1);
-  g.div_sub_plane = make_fastdiv(g.sub_plane > 0 ? g.sub_plane : 1);
-  if (g.slab) g.site_blocks = ((geo.Vh >> 3) + c.block - 1) / c.block;
-  else g.site_blocks = (geo.Vh + c.block - 1) / c.block;
-  return g;
-}
-
-static unsigned grid_blocks(const DslashGeom& g) {
-  if (g.slab) return 8u * (unsigned)(g.site_blocks * g.ngroups);
-  const unsigned per = (unsigned)((g.site_blocks * g.ngroups + 7) / 8);
-  return 8u * per;
-}
-
-static FieldView fview(const Field& f) { return FieldView{f.ptr, f.stride, f.nrhs}; }
-static FieldView fview(const Field* f) { return f ? fview(*f) : FieldView{nullptr, 0, 0}; }
-
-// LDS reserved per workgroup (unused by the kernel) so that at most `wgs`
-// workgroups fit on a CU (160 KiB of LDS); 0 leaves occupancy to registers.
-static size_t lds_for(int wgs) {
-  if (wgs < 2) return 0;
-  const size_t per = (size_t(160) * 1024 / wgs) / 512 * 512;
-  return per > 63488 ? 63488 : per;  // below the 64 KiB per-workgroup limit with the static LDS
-}
-
-template <class S, bool DAGGER, bool XPAY, int NR, int RECON>
-static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
-                       const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
-                       typename S::real a, int p, const int* active, double* partials) {
-  switch (dot) {
-    case DOT_YO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    case DOT_OX:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    case DOT_OO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    default:
-      dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-  }
-}
-
-template <class S, int NR, int RECON>
-static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
-  LaunchCfg c = cfg;
-  c.nr = NR;  // the RHS slots of the kernel actually launched
-  DslashGeom g = make_dgeom(gg->geom, d.out.nrhs, c);
-  g.tgauge = gg->tgauge;
-  const char* links = static_cast<const char*>(gg->link[S::prec]);
-  const unsigned grid = grid_blocks(g);
-  FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
-  using R = typename S::real;
-  const R ar = static_cast<R>(d.a);
-  const int dot = d.xpay ? d.dot : DOT_NONE;
-  if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true, NR, RECON>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, true, false, NR, RECON>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-  } else {
-    if (d.xpay) launch_dot<S, false, true, NR, RECON>(dot, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, false, false, NR, RECON>(DOT_NONE, grid, c.block, lds_for(c.wgs), s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-  }
-}
-
-// Threads carry at least two RHS slots: with one, the compiler keeps every
-// gather of a site in flight and runs out of registers (a single RHS leaves
-// the second slot empty).  8-real links are built for two slots only (their
-// rebuild is long; wider shapes gain little when links are a small part of
-// the bytes).
-template <class S>
-static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
-  if (gg->recon == 8) {
-    launch_nr<S, 2, 8>(gg, d, c, s);
-    return;
-  }
-  switch (c.nr) {
-    case 3: launch_nr<S, 3, 12>(gg, d, c, s); break;
-    case 4: launch_nr<S, 4, 12>(gg, d, c, s); break;
-    default: launch_nr<S, 2, 12>(gg, d, c, s); break;
-  }
-}
+void launch_dslash_fp64(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_fp32(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_i16(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_f16(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
 
 void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
                        hipStream_t s) {
   switch (prec) {
-    case WD_FP64: launch_cfg<SF64>(g, d, c, s); break;
-    case WD_FP32: launch_cfg<SF32>(g, d, c, s); break;
-    case WD_HALF_I16: launch_cfg<SI16>(g, d, c, s); break;
-    default: launch_cfg<SF16>(g, d, c, s); break;
+    case WD_FP64: launch_dslash_fp64(g, d, c, s); break;
+    case WD_FP32: launch_dslash_fp32(g, d, c, s); break;
+    case WD_HALF_I16: launch_dslash_i16(g, d, c, s); break;
+    default: launch_dslash_f16(g, d, c, s); break;
   }
 }
 
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
   if (prec < WD_FP64 || prec > WD_HALF_F16) return hipErrorInvalidValue;
+  if (d.dot == DOT_RES && (prec != WD_FP64 || !d.xpay || !d.y || d.dagger)) return hipErrorInvalidValue;
   LaunchCfg c = tuned_dslash_config(g, prec, d, s);
   // A fused dot sums each workgroup's sites into one partial record; with one
   // sub-slab those site sets are fixed whatever nr and gslow are, so the

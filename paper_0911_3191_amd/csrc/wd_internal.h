@@ -60,7 +60,9 @@ namespace wd {
 
 // ---- launchers (defined in the .hip files; all asynchronous on `s`) -------------
 constexpr int kMaxDotHost = 4;  // doubles per partial record
-enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3 };
+// DOT_RES (FP64 only): out = y - (xpay + a D in), the residual of a reliable
+// update, with |out|^2 partials.
+enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4 };
 
 // Full argument set of one dslash launch.  out = D in, or, with xpay set,
 // out = *xpay + a * D in; with xpay and dot set, per-block FP64 partials of
@@ -89,6 +91,7 @@ struct LaunchCfg {
   int link_nt = 0;  // link loads marked streaming
   int out_nt = 0;   // output stores marked streaming
   int wgs = 0;      // cap on workgroups per CU (0: registers decide)
+  int lds = 0;      // 16-bit formats: stage x/y neighbours in LDS
 };
 void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
                        hipStream_t s);
@@ -164,8 +167,6 @@ hipError_t blas_zero(const Geom& g, wd_prec pr, Field f, const int* mask, hipStr
 hipError_t blas_norm2(const Geom& g, wd_prec pr, Field f, const int* mask, double* partials,
                       hipStream_t s);
 hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int* mask, hipStream_t s);
-hipError_t blas_residual(const Geom& g, Field r64, Field b64, const int* mask, double* partials,
-                         hipStream_t s);
 hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s);
 hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
                          const int* mask, double* partials, hipStream_t s);

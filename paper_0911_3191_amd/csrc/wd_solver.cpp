@@ -116,7 +116,8 @@ static hipError_t mhat_into(wd_solver* h, wd_prec prec, const Field& out, const 
 
 static hipError_t fin(wd_solver* h, int stage, const int* mask) {
   // the stages that follow a dslash with a fused dot read the dslash's partial records
-  const bool after_dslash = stage == FIN_BICG_ALPHA || stage == FIN_BICG_OMEGA || stage == FIN_CG_ALPHA;
+  const bool after_dslash =
+      stage == FIN_BICG_ALPHA || stage == FIN_BICG_OMEGA || stage == FIN_CG_ALPHA || stage == FIN_TRUE;
   return solver_finalize(stage, h->nrhs, after_dslash ? h->nb_dslash : h->nb, h->partials, h->sc,
                          h->fl, h->active, h->rumask, mask, h->prm.delta, h->prm.tol, h->prm.restart,
                          h->s);
@@ -154,9 +155,10 @@ static hipError_t iteration_body(wd_solver* h) {
 }
 
 // FP64 r = b_hat - M_hat x for the RHS in mask, then the convergence test.
+// The subtraction from b_hat and |r|^2 are fused into the second dslash.
 static hipError_t true_residual(wd_solver* h, const int* mask) {
-  WD_TRY(mhat_into(h, WD_FP64, h->r, h->x, h->to64, 0, DOT_NONE, nullptr, mask));
-  WD_TRY(blas_residual(h->geom, h->r, h->bhat, mask, h->partials, h->s));
+  WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, nullptr, 0.0, DOT_NONE, nullptr, mask));
+  WD_TRY(dslash_into(h, WD_FP64, h->r, h->to64, 0, 0, &h->x, -h->kappa * h->kappa, DOT_RES, &h->bhat, mask));
   WD_TRY(fin(h, FIN_TRUE, mask));
   return hipSuccess;
 }

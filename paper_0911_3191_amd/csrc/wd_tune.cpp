@@ -1,6 +1,7 @@
 // Autotuner for the dslash launch shape: right-hand sides per thread (nr),
 // y-sub-slabs of an XCD's sweep (nsub, shortens the reuse distance of the
-// t-neighbours) and the cache policy of the link loads (link_nt).
+// t-neighbours), the cache policy of the link loads (link_nt) and, for the
+// 16-bit formats, LDS staging of the x/y neighbours (lds).
 //
 // The first eager launch for a (lattice, precision, nrhs) times each
 // candidate with HIP events on the caller's stream, using the plain
@@ -9,9 +10,9 @@
 // output aliases their xpay source, use the default shape instead and do not
 // tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
 // across processes (one "Lx Ly Lz Lt prec nrhs flags nr block gslow nsub
-// link_nt" line per entry, flags = 1 for 8-real links + 2 for temporal
+// link_nt lds" line per entry, flags = 1 for 8-real links + 2 for temporal
 // gauge); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
-// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs]]]" forces a shape
+// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs[,lds]]]]" forces a shape
 // (the RHS-group-slowest order, streaming output stores and the occupancy
 // cap are not searched: none paid on the lattices measured).
 #include <hip/hip_runtime.h>
@@ -55,12 +56,15 @@ void load_cache_locked() {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  int lx, ly, lz, lt, prec, nrhs, flags, nr, block, gslow, nsub, nt;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &flags, &nr,
-                     &block, &gslow, &nsub, &nt) == 12) {
+  int lx, ly, lz, lt, prec, nrhs, flags, nr, block, gslow, nsub, nt, lds;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &flags, &nr,
+                     &block, &gslow, &nsub, &nt, &lds) == 13) {
     if (nr >= 1 && nr <= 4 && block == 256 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
-        (nt == 0 || nt == 1))
-      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, flags}] = LaunchCfg{nr, block, gslow, nsub, nt};
+        (nt == 0 || nt == 1) && (lds == 0 || lds == 1)) {
+      LaunchCfg c{nr, block, gslow, nsub, nt};
+      c.lds = lds;
+      g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, flags}] = c;
+    }
   }
   std::fclose(f);
 }
@@ -70,9 +74,9 @@ void save_entry_locked(const Key& k, const LaunchCfg& c) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
                std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), std::get<5>(k), c.nr, c.block, c.gslow,
-               c.nsub, c.link_nt);
+               c.nsub, c.link_nt, c.lds);
   std::fclose(f);
 }
 
@@ -126,17 +130,20 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
     if (g->recon == 8 && nr > 2) break;  // 8-real kernels exist for two slots
     for (int nsub = 1; nsub <= (slab ? 4 : 1); nsub *= 2) {
       if (g->geom.L[1] % nsub) continue;
-      for (int nt = 0; nt <= 1; ++nt) {
+      for (int v = 0; v < 4; ++v) {
+        const int nt = v & 1, lds = v >> 1;
+        if (lds && !(is_half(prec) && nr <= 3 && g->recon == 12 && slab)) continue;
         const int gslow = 0;
-        const LaunchCfg c{nr, 256, gslow, nsub, nt};
+        LaunchCfg c{nr, 256, gslow, nsub, nt};
+        c.lds = lds;
         // the better of two timings, so a clock ramp-up does not decide
         float ms = time_cfg(g, prec, plain, c, s);
         const float ms2 = time_cfg(g, prec, plain, c, s);
         if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
         if (verbose())
-          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: nr %d nsub %d link_nt %d -> %.1f us\n",
+          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: nr %d nsub %d link_nt %d lds %d -> %.1f us\n",
                        g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs,
-                       nr, nsub, nt, ms * 1e3f);
+                       nr, nsub, nt, lds, ms * 1e3f);
         if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
           best_ms = ms;
           best = c;
@@ -153,11 +160,11 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
   const int nrhs = d.out.nrhs;
   // WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt]" forces one shape (tests sweep them with it)
   if (const char* f = std::getenv("WD_DSLASH_SHAPE")) {
-    int nr = 1, gslow = 0, nsub = 1, nt = 0, ont = 0, wgs = 0;
-    const int n = std::sscanf(f, "%d,%d,%d,%d,%d,%d", &nr, &gslow, &nsub, &nt, &ont, &wgs);
+    int nr = 1, gslow = 0, nsub = 1, nt = 0, ont = 0, wgs = 0, lds = 0;
+    const int n = std::sscanf(f, "%d,%d,%d,%d,%d,%d,%d", &nr, &gslow, &nsub, &nt, &ont, &wgs, &lds);
     if (n >= 3 && nr >= 1 && nr <= 4 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
-        (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8)
-      return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs};
+        (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8 && (lds == 0 || lds == 1))
+      return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs, lds};
   }
   const Key k = key_of(g, prec, nrhs);
   {

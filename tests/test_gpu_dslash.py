@@ -100,8 +100,9 @@ def test_multi_rhs_equals_single_rhs_bitwise(prec):
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("dims", [(4, 6, 8, 4), (6, 4, 16, 2), (6, 4, 6, 10)], ids=lambda d: "x".join(map(str, d)))
 def test_every_launch_shape_gives_identical_results(prec, dims, monkeypatch):
-    """RHS per thread, RHS-group order and y-sub-slabs only redistribute work:
-    every shape must give the same bits, and match the oracle."""
+    """RHS per thread, RHS-group order, y-sub-slabs and LDS staging only
+    redistribute work: every shape must give the same bits, and match the
+    oracle."""
     U = wdinputs.gauge_random(dims, 0.5, 61)
     s = Setup(dims, U)
     srcs = wdinputs.spinor_gaussian(dims, 62, nrhs=3)
@@ -110,11 +111,12 @@ def test_every_launch_shape_gives_identical_results(prec, dims, monkeypatch):
     for nr in (1, 2, 3, 4):
         for gslow in (0, 1):
             for nsub in (1, 2, 3):
-                monkeypatch.setenv("WD_DSLASH_SHAPE", f"{nr},{gslow},{nsub}")
-                fout = s.field(prec, 3)
-                wd.wilson_dslash(s.gauge, fout, fin, 0, 1, prec, 3)
-                results[(nr, gslow, nsub)] = s.decode(prec, fout, 3)
-    ref = results[(1, 0, 1)]
+                for lds in ((0, 1) if prec in ("i16", "f16") else (0,)):
+                    monkeypatch.setenv("WD_DSLASH_SHAPE", f"{nr},{gslow},{nsub},0,0,0,{lds}")
+                    fout = s.field(prec, 3)
+                    wd.wilson_dslash(s.gauge, fout, fin, 0, 1, prec, 3)
+                    results[(nr, gslow, nsub, lds)] = s.decode(prec, fout, 3)
+    ref = results[(1, 0, 1, 0)]
     for key, val in results.items():
         assert np.array_equal(val, ref), key
     for k in range(3):
