@@ -111,6 +111,62 @@ def profiled_traffic(kernel: str, dims) -> dict | None:
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
+def other_configs(wd, torch, wdinputs, stream) -> dict:
+    """8^4 plain FP64 BiCGstab to 1e-10; 24^3x32 Gaussian source by RU-BiCGstab
+    with FP32, int16 and binary16 inner solvers against FP64 (eps 0.3, seed 2,
+    kappa 0.124); 24^3x32 CG on 12 point sources in FP32 and binary16 storage
+    under hipGraph (eps 0.5, seed 3, kappa 0.1245).  Each solve runs once
+    untimed (launch shapes are tuned) and once timed."""
+    dev = torch.device("cuda:0")
+
+    def timed(gauge, lat, kappa, b, solver, **kw):
+        p = wd.solve_params(maxiter=20000, use_graph=True, **kw)
+        ws = wd.new_workspace(lat, p, solver)
+        fn = wd.bicgstab_solve if solver == "bicgstab" else wd.cg_solve
+        x = torch.zeros_like(b)
+        with torch.cuda.stream(stream):
+            fn(gauge, kappa, x, b, p, ws, stream)
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        with torch.cuda.stream(stream):
+            st, infos = fn(gauge, kappa, x, b, p, ws, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        return {"seconds": round(dt, 4), "status": st, "iters_max": max(i["iters"] for i in infos),
+                "reliable_updates_max": max(i["reliable_updates"] for i in infos),
+                "true_rel_resid_max": max(i["true_rel_resid"] for i in infos)}
+
+    out = {}
+    dims = (8, 8, 8, 8)
+    lat = wd.lattice(dims)
+    U = torch.from_numpy(wdinputs.gauge_random(dims, 0.3, 1)).to(dev)
+    g = wd.Gauge(lat, U, ("fp64",))
+    b = torch.from_numpy(wdinputs.spinor_gaussian(dims, 1001)).to(dev).reshape(1, -1)
+    out["8x8x8x8_fp64_bicgstab_1e-10"] = timed(g, lat, 0.12, b, "bicgstab", tol=1e-10, inner="fp64", delta=0.0)
+    dims = (24, 24, 24, 32)
+    lat = wd.lattice(dims)
+    U = torch.from_numpy(wdinputs.gauge_random(dims, 0.3, 2)).to(dev)
+    g = wd.Gauge(lat, U)
+    b = torch.from_numpy(wdinputs.spinor_gaussian(dims, 1002)).to(dev).reshape(1, -1)
+    c2 = {"fp64": timed(g, lat, 0.124, b, "bicgstab", tol=1e-12, inner="fp64", delta=0.0)}
+    for inner in ("fp32", "i16", "f16"):
+        c2[inner] = timed(g, lat, 0.124, b, "bicgstab", tol=1e-12, inner=inner, delta=0.1)
+        c2[inner]["speedup_vs_fp64"] = round(c2["fp64"]["seconds"] / c2[inner]["seconds"], 2)
+    out["24x24x24x32_ru_bicgstab_1e-12"] = c2
+    U = torch.from_numpy(wdinputs.gauge_random(dims, 0.5, 3)).to(dev)
+    g = wd.Gauge(lat, U, ("fp64", "fp32", "f16"))
+    V = int(np.prod(dims))
+    bp = torch.zeros((NRHS, V, 4, 3, 2), dtype=torch.float64, device=dev)
+    for sp in range(4):
+        for c in range(3):
+            bp[3 * sp + c, 0, sp, c, 0] = 1.0
+    out["24x24x24x32_cg_12_point_sources_1e-12"] = {
+        inner: timed(g, lat, 0.1245, bp, "cg", tol=1e-12, inner=inner, delta=0.1, nrhs=NRHS)
+        for inner in ("fp32", "f16")}
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +177,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-defect-correction", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the Poisson serving run (0: skip it)")
@@ -326,6 +383,12 @@ def main():
     log(f"copy: {ncopy * 8 / 1e9:.2f} GB read + written at {copy_gbs:.0f} GB/s")
     del src, dst
 
+    # ---- the smaller configurations: time to solution, mixed against FP64 ----
+    others = None
+    if not args.no_other_configs:
+        others = other_configs(wd, torch, wdinputs, stream)
+        log(f"other configurations: {others}")
+
     # ---- serving: Poisson arrivals over 8 resident fields of three lattice sizes ----
     serve = None
     if args.serve_requests > 0:
@@ -410,6 +473,7 @@ def main():
                              "defect_correction": dc},
         "dslash_single_rhs": table,
         "copy_GBps": round(copy_gbs, 1),
+        "other_configs": others,
         "serve": serve,
         "cpu_baseline": cpu,
     }

@@ -379,6 +379,14 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       break;
     }
     case FIN_BICG_OMEGA: {  // omega = <t, s> / <t, t>
+      if (v[2] == 0.0 && v[0] == 0.0 && v[1] == 0.0) {
+        // t = M_hat s = 0 means s = 0: the step already solved the system and
+        // omega is arbitrary; 1 keeps the next beta finite (r becomes 0 and a
+        // reliable update follows)
+        s[SC_OMEGA] = 1.0;
+        s[SC_OMEGA + 1] = 0.0;
+        break;
+      }
       if (!(v[2] > 0.0) || !isfinite(v[2])) {
         f[FL_BREAK] = stage + 1;
         active[rhs] = 0;

@@ -61,7 +61,8 @@ def test_validation_rejects_bad_lattices_and_arguments(lib):
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("restart", 2, b"restart"), ("delta", 1.0, b"delta"), ("nrhs", 0, b"nrhs"), ("tol", 0.0, b"tol"),
+    ("restart", 2, b"restart"), ("delta", 1.0, b"delta"), ("nrhs", 0, b"nrhs"), ("nrhs", 65, b"nrhs"),
+    ("tol", 0.0, b"tol"),
     ("maxiter", 0, b"maxiter"), ("x0_given", 1, b"x0_given")])
 def test_solver_parameters_are_validated_before_any_launch(lib, field, value, msg):
     import paper_0911_3191_amd as wd

@@ -186,3 +186,21 @@ def test_accuracy_cdf_uniform_vector():
         wd.wilson_mat_pc(s.gauge, 0.12, fout, fin, tmp, 0, prec)
         dev = np.abs(s.decode(prec, fout) - ref).max() / (scale * ulp[prec])
         assert dev < 200, f"{prec}: first deviation at {dev:.1f} ulp"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_sixty_four_rhs_in_one_launch_equal_single_rhs(prec):
+    """The largest batch the ABI accepts (64 RHS, 32 groups of two slots)."""
+    dims = (4, 4, 8, 4)
+    U = wdinputs.gauge_random(dims, 0.5, 71)
+    s = Setup(dims, U, precs=("fp64", prec))
+    srcs = wdinputs.spinor_gaussian(dims, 72, nrhs=64)
+    fin = s.encode_full(prec, srcs, 1, nrhs=64)
+    fout = s.field(prec, 64)
+    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 64)
+    multi = s.decode(prec, fout, 64)
+    for k in (0, 1, 31, 62, 63):
+        f1 = s.encode_full(prec, srcs[k], 1)
+        o1 = s.field(prec)
+        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        assert np.array_equal(s.decode(prec, o1), multi[k]), k

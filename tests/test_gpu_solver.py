@@ -199,3 +199,27 @@ def test_config2_defect_correction_against_reliable_updates():
         assert st == wd.WD_OK and oracle.true_relres(dims, U, kappa, b, x) <= 1e-12
         res[inner] = (ru["iters"], dc["iters"])
     print("config2 iterations (reliable updates, defect correction):", res)
+
+
+def test_smallest_lattice_mixed_solve():
+    """2^4: every neighbour wraps; both parities have 8 sites."""
+    dims, kappa = (2, 2, 2, 2), 0.124
+    U = wdinputs.gauge_random(dims, 0.5, 74)
+    s = Setup(dims, U)
+    b = wdinputs.spinor_gaussian(dims, 75)
+    for solver in ("bicgstab", "cg"):
+        st, x, info = run(s, solver, b, kappa, tol=1e-12, inner="f16", delta=0.1, maxiter=2000)
+        assert st == wd.WD_OK, (solver, info)
+        assert oracle.true_relres(dims, U, kappa, b, x) <= 1e-12
+
+
+def test_vanishing_kappa_returns_the_source():
+    """kappa -> 0: 1 - kappa D -> 1, so x = b within a few iterations."""
+    dims = (4, 4, 4, 4)
+    U = wdinputs.gauge_random(dims, 0.3, 76)
+    s = Setup(dims, U)
+    b = wdinputs.spinor_gaussian(dims, 77)
+    st, x, info = run(s, "bicgstab", b, 1e-14, tol=1e-12, inner="fp32", delta=0.1)
+    assert st == wd.WD_OK
+    assert np.linalg.norm(x.reshape(b.shape) - b) <= 1e-11 * np.linalg.norm(b)
+    assert info["iters"] <= 6
