@@ -170,6 +170,24 @@ wd_status wd_spinor_encode_full(const wd_lattice *lat, wd_prec prec, int32_t nrh
 wd_status wd_spinor_decode_full(const wd_lattice *lat, wd_prec prec, int32_t nrhs, int32_t parity,
                                 double *canon_full, const void *field, void *stream);
 
+/* Spin bases of encoded fields (Appendix B).  Canonical arrays are always in
+ * the DeGrand-Rossi basis; every encode, decode and operator entry point above
+ * works on DeGrand-Rossi fields.  The UKQCD ("non-relativistic") basis is the
+ * rotation psi_UK = S psi_DR with S = [[0, 1, 0, 1], [-1, 0, -1, 0],
+ * [0, 1, 0, -1], [-1, 0, 1, 0]] / sqrt(2), in which gamma_t is
+ * diag(1, 1, -1, -1): a temporal hop then reads half a spinor.  The solvers
+ * rotate their fields into it internally. */
+#define WD_BASIS_DEGRAND_ROSSI 0
+#define WD_BASIS_UKQCD 1
+
+/* As wd_spinor_encode / wd_spinor_decode, with the field in spin basis
+ * `basis` (the rotation is applied in FP64 before storage / after loading).
+ * WD_EINVAL for an unknown basis. */
+wd_status wd_spinor_encode_basis(const wd_lattice *lat, wd_prec prec, int32_t nrhs, int32_t basis,
+                                 void *field, const double *canon, void *stream);
+wd_status wd_spinor_decode_basis(const wd_lattice *lat, wd_prec prec, int32_t nrhs, int32_t basis,
+                                 double *canon, const void *field, void *stream);
+
 /* ---- operators ------------------------------------------------------------------ */
 
 /* Hopping term restricted to parities (Eq. 1): out_p = D_{p,1-p} in_{1-p}, or
@@ -179,6 +197,12 @@ wd_status wd_spinor_decode_full(const wd_lattice *lat, wd_prec prec, int32_t nrh
  * parity.  No factor kappa.  Asynchronous on stream. */
 wd_status wilson_dslash(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
                         int32_t dagger, wd_prec prec, int32_t nrhs, void *stream);
+
+/* wilson_dslash on fields in spin basis `basis` (WD_BASIS_*); the result is
+ * S D S^T applied to in, i.e. the same operator written in that basis
+ * (Appendix B).  WD_EINVAL for an unknown basis. */
+wd_status wilson_dslash_basis(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
+                              int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void *stream);
 
 /* Even-odd operator (Eq. 2): out_e = in_e - kappa^2 D_eo D_oe in_e (dagger = 1:
  * the adjoint M_hat^dagger).  tmp_odd is an odd-parity field of the same

@@ -17,6 +17,8 @@ __all__ = [
     "Lattice", "WDError", "Gauge", "PREC", "WD_FP64", "WD_FP32", "WD_HALF_I16", "WD_HALF_F16",
     "lattice", "prec_of", "wd_gauge_bytes", "wd_spinor_bytes", "new_field", "wd_spinor_encode",
     "wd_spinor_decode", "wd_spinor_encode_full", "wd_spinor_decode_full", "wilson_dslash",
+    "wd_spinor_encode_basis", "wd_spinor_decode_basis", "wilson_dslash_basis",
+    "WD_BASIS_DEGRAND_ROSSI", "WD_BASIS_UKQCD",
     "wilson_mat_pc", "mdagm", "gauge_fix_temporal", "wd_gauge_rotate_spinor", "WD_GAUGE_TEMPORAL",
 ]
 
@@ -47,6 +49,7 @@ def new_field(lat: Lattice, prec, nrhs: int = 1, device="cuda"):
 
 
 WD_GAUGE_TEMPORAL = 1
+WD_BASIS_DEGRAND_ROSSI, WD_BASIS_UKQCD = 0, 1
 
 
 class Gauge:
@@ -111,6 +114,16 @@ def wd_spinor_decode(lat, prec, nrhs, canon, field, stream=None):
                                         stream_ptr(stream)), "wd_spinor_decode")
 
 
+def wd_spinor_encode_basis(lat, prec, nrhs, basis, field, canon, stream=None):
+    return check(lib().wd_spinor_encode_basis(ctypes.byref(lat), prec_of(prec), nrhs, basis, ptr(field),
+                                              ptr(canon), stream_ptr(stream)), "wd_spinor_encode_basis")
+
+
+def wd_spinor_decode_basis(lat, prec, nrhs, basis, canon, field, stream=None):
+    return check(lib().wd_spinor_decode_basis(ctypes.byref(lat), prec_of(prec), nrhs, basis, ptr(canon),
+                                              ptr(field), stream_ptr(stream)), "wd_spinor_decode_basis")
+
+
 def wd_spinor_encode_full(lat, prec, nrhs, parity, field, canon_full, stream=None):
     return check(lib().wd_spinor_encode_full(ctypes.byref(lat), prec_of(prec), nrhs, parity, ptr(field),
                                              ptr(canon_full), stream_ptr(stream)), "wd_spinor_encode_full")
@@ -126,6 +139,12 @@ def wilson_dslash(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nr
                   stream=None):
     return check(lib().wilson_dslash(gauge.handle, ptr(out), ptr(inp), out_parity, dagger, prec_of(prec),
                                      nrhs, stream_ptr(stream)), "wilson_dslash")
+
+
+def wilson_dslash_basis(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1,
+                        basis: int = 1, stream=None):
+    return check(lib().wilson_dslash_basis(gauge.handle, ptr(out), ptr(inp), out_parity, dagger,
+                                           prec_of(prec), nrhs, basis, stream_ptr(stream)), "wilson_dslash_basis")
 
 
 def wilson_mat_pc(gauge: Gauge, kappa: float, out, inp, tmp_odd, dagger: int, prec, nrhs: int = 1,

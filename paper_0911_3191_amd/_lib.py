@@ -76,8 +76,13 @@ def lib():
         for name in ("wd_spinor_encode_full", "wd_spinor_decode_full"):
             getattr(L, name).argtypes = [lp, i32, i32, i32, vp, vp, vp]
             getattr(L, name).restype = i32
+        for name in ("wd_spinor_encode_basis", "wd_spinor_decode_basis"):
+            getattr(L, name).argtypes = [lp, i32, i32, i32, vp, vp, vp]
+            getattr(L, name).restype = i32
         L.wilson_dslash.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
         L.wilson_dslash.restype = i32
+        L.wilson_dslash_basis.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp]
+        L.wilson_dslash_basis.restype = i32
         L.wilson_mat_pc.argtypes = [vp, dbl, vp, vp, vp, i32, i32, i32, vp]
         L.wilson_mat_pc.restype = i32
         L.mdagm.argtypes = [vp, dbl, vp, vp, vp, vp, i32, i32, vp]

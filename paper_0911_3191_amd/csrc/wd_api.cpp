@@ -217,32 +217,44 @@ size_t wd_spinor_bytes(const wd_lattice* lat, wd_prec prec, int32_t nrhs) {
   return spinor_field_bytes(make_geom(*lat), prec, nrhs);
 }
 
-wd_status wd_spinor_encode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, void* field,
-                           const double* canon, void* stream) {
+wd_status wd_spinor_encode_basis(const wd_lattice* lat, wd_prec prec, int32_t nrhs, int32_t basis,
+                                 void* field, const double* canon, void* stream) {
   g_last_error.clear();
   wd_status st = check_lattice(lat);
   if (st) return st;
   if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if (basis != WD_BASIS_DEGRAND_ROSSI && basis != WD_BASIS_UKQCD) return fail(WD_EINVAL, "unknown spin basis");
   if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) || (st = check_ptr(canon, "canon")))
     return st;
   const Geom g = make_geom(*lat);
   return hip_status(launch_spinor_encode(g, prec, field_of(g, field, nrhs), canon,
-                                         static_cast<hipStream_t>(stream)),
+                                         static_cast<hipStream_t>(stream), basis),
                     "spinor encode");
 }
 
-wd_status wd_spinor_decode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, double* canon,
-                           const void* field, void* stream) {
+wd_status wd_spinor_decode_basis(const wd_lattice* lat, wd_prec prec, int32_t nrhs, int32_t basis,
+                                 double* canon, const void* field, void* stream) {
   g_last_error.clear();
   wd_status st = check_lattice(lat);
   if (st) return st;
   if (!prec_ok(prec)) return fail(WD_EINVAL, "unknown precision");
+  if (basis != WD_BASIS_DEGRAND_ROSSI && basis != WD_BASIS_UKQCD) return fail(WD_EINVAL, "unknown spin basis");
   if ((st = check_nrhs(nrhs)) || (st = check_ptr(field, "field")) || (st = check_ptr(canon, "canon")))
     return st;
   const Geom g = make_geom(*lat);
   return hip_status(launch_spinor_decode(g, prec, canon, field_of(g, const_cast<void*>(field), nrhs),
-                                         static_cast<hipStream_t>(stream)),
+                                         static_cast<hipStream_t>(stream), basis),
                     "spinor decode");
+}
+
+wd_status wd_spinor_encode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, void* field,
+                           const double* canon, void* stream) {
+  return wd_spinor_encode_basis(lat, prec, nrhs, WD_BASIS_DEGRAND_ROSSI, field, canon, stream);
+}
+
+wd_status wd_spinor_decode(const wd_lattice* lat, wd_prec prec, int32_t nrhs, double* canon,
+                           const void* field, void* stream) {
+  return wd_spinor_decode_basis(lat, prec, nrhs, WD_BASIS_DEGRAND_ROSSI, canon, field, stream);
 }
 
 wd_status wd_spinor_encode_full(const wd_lattice* lat, wd_prec prec, int32_t nrhs, int32_t parity,
@@ -278,19 +290,25 @@ wd_status wd_spinor_decode_full(const wd_lattice* lat, wd_prec prec, int32_t nrh
                     "spinor decode (full lattice)");
 }
 
-wd_status wilson_dslash(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
-                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
+wd_status wilson_dslash_basis(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
+                              int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void* stream) {
   g_last_error.clear();
   wd_status st = check_gauge(g, prec);
   if (st) return st;
   if ((st = check_nrhs(nrhs)) || (st = check_ptr(out, "out")) || (st = check_ptr(in, "in"))) return st;
   if (out_parity != 0 && out_parity != 1) return fail(WD_EINVAL, "out_parity must be 0 or 1");
   if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  if (basis != WD_BASIS_DEGRAND_ROSSI && basis != WD_BASIS_UKQCD) return fail(WD_EINVAL, "unknown spin basis");
   if (out == in) return fail(WD_EINVAL, "out and in must not alias");
   const Geom& geo = g->geom;
   return hip_status(launch_dslash(g, prec, field_of(geo, out, nrhs), field_of(geo, const_cast<void*>(in), nrhs),
-                                  out_parity, dagger, nullptr, 0.0, static_cast<hipStream_t>(stream)),
+                                  out_parity, dagger, nullptr, 0.0, static_cast<hipStream_t>(stream), basis),
                     "wilson_dslash");
+}
+
+wd_status wilson_dslash(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
+                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
+  return wilson_dslash_basis(g, out, in, out_parity, dagger, prec, nrhs, WD_BASIS_DEGRAND_ROSSI, stream);
 }
 
 wd_status wilson_mat_pc(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,

@@ -79,10 +79,10 @@ __device__ __forceinline__ uint16_t f_to_h16(float v) {
   return __half_as_ushort(__float2half_rn(v));
 }
 // Pins a binary32 value in a register as computed.  Without it the compiler
-// fuses a multiply feeding a binary16 conversion into one mixed-precision FMA
-// whose rounding differs from "round the product to binary32, then to
-// binary16", which is how the 16-bit format is defined.  (Empty asm, no
-// memory access.)
+// fuses a multiply feeding a binary16 conversion into one mixed-precision FMA,
+// or folds a double -> binary32 -> binary16 chain into one direct rounding;
+// both round differently from "round to binary32, then to binary16", which is
+// how the 16-bit formats are defined.  (Empty asm, no memory access.)
 __device__ __forceinline__ float pin_f32(float x) {
   asm volatile("" : "+v"(x));
   return x;

@@ -8,19 +8,26 @@ void launch_dslash_fp64(const wd_gauge* g, const DslashArgs& d, const LaunchCfg&
 void launch_dslash_fp32(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
 void launch_dslash_i16(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
 void launch_dslash_f16(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_fp64_uk(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_fp32_uk(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_i16_uk(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
+void launch_dslash_f16_uk(const wd_gauge* g, const DslashArgs& d, const LaunchCfg& c, hipStream_t s);
 
 void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
                        hipStream_t s) {
+  const bool uk = d.basis == kBasisUK;
   switch (prec) {
-    case WD_FP64: launch_dslash_fp64(g, d, c, s); break;
-    case WD_FP32: launch_dslash_fp32(g, d, c, s); break;
-    case WD_HALF_I16: launch_dslash_i16(g, d, c, s); break;
-    default: launch_dslash_f16(g, d, c, s); break;
+    case WD_FP64: uk ? launch_dslash_fp64_uk(g, d, c, s) : launch_dslash_fp64(g, d, c, s); break;
+    case WD_FP32: uk ? launch_dslash_fp32_uk(g, d, c, s) : launch_dslash_fp32(g, d, c, s); break;
+    case WD_HALF_I16: uk ? launch_dslash_i16_uk(g, d, c, s) : launch_dslash_i16(g, d, c, s); break;
+    default: uk ? launch_dslash_f16_uk(g, d, c, s) : launch_dslash_f16(g, d, c, s); break;
   }
 }
 
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s) {
   if (prec < WD_FP64 || prec > WD_HALF_F16) return hipErrorInvalidValue;
+  if (d.basis != kBasisDR && d.basis != kBasisUK) return hipErrorInvalidValue;
+  if (d.basis == kBasisDR && d.xpay && d.dot != DOT_NONE) return hipErrorInvalidValue;
   if (d.dot == DOT_RES && (prec != WD_FP64 || !d.xpay || !d.y || d.dagger)) return hipErrorInvalidValue;
   LaunchCfg c = tuned_dslash_config(g, prec, d, s);
   // A fused dot sums each workgroup's sites into one partial record; with one
@@ -32,7 +39,7 @@ hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d
 }
 
 hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int out_parity,
-                         int dagger, const Field* xpay_src, double a, hipStream_t s) {
+                         int dagger, const Field* xpay_src, double a, hipStream_t s, int basis) {
   DslashArgs d;
   d.out = out;
   d.in = in;
@@ -40,6 +47,7 @@ hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, i
   d.dagger = dagger;
   d.xpay = xpay_src;
   d.a = a;
+  d.basis = basis;
   return launch_dslash_ex(g, prec, d, s);
 }
 

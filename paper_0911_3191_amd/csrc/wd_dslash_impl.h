@@ -47,6 +47,17 @@ template <> struct Gamma<1> { static constexpr int P0 = 1, P1 = 0, PH0 = 2, PH1 
 template <> struct Gamma<2> { static constexpr int P0 = 0, P1 = 1, PH0 = 1, PH1 = 3; };
 template <> struct Gamma<3> { static constexpr int P0 = 0, P1 = 1, PH0 = 0, PH1 = 0; };
 
+// Spin bases of the fields a launch works on (Appendix B).  In the UKQCD
+// ("non-relativistic") basis psi' = S psi with
+//   S = [[0, 1, 0, 1], [-1, 0, -1, 0], [0, 1, 0, -1], [-1, 0, 1, 0]] / sqrt(2),
+// gamma_x and gamma_z are those of the DeGrand-Rossi basis, gamma_y changes
+// sign (A_y = [[0, 1], [-1, 0]]) and gamma_t = diag(1, 1, -1, -1): the
+// temporal projectors 1 +- gamma_t keep only the upper or only the lower two
+// spins (times 2), so a temporal hop loads half a spinor.
+template <int MU, int BASIS>
+struct GammaB : Gamma<MU> {};
+template <> struct GammaB<1, kBasisUK> { static constexpr int P0 = 1, P1 = 0, PH0 = 0, PH1 = 2; };
+
 // n / d for n < 2^31 with a precomputed multiplier (round-up method).
 struct FastDiv {
   uint32_t m, s;
@@ -370,14 +381,12 @@ __device__ __forceinline__ cx<R> cmacc(cx<R> acc, cx<R> a, cx<R> b) {
   return {fmar(a.im, b.im, fmar(a.re, b.re, acc.re)), fmar(-a.im, b.re, fmar(a.re, b.im, acc.im))};
 }
 
-// Accumulate one hop: acc += scale * (1 + s gamma_mu) (W psi), W = U or U^dagger
-// (scale carries the 16-bit norm and the t-boundary sign).
 // Multiply the projected half spinor h by W = U or U^dagger, expand to four
 // spins and accumulate: acc += scale * (1 + s gamma_mu) (W psi), where scale
 // carries the 16-bit norm and the t-boundary sign.
-template <int MU, int S, bool DAG_LINK, typename R>
+template <int MU, int S, bool DAG_LINK, int BASIS, typename R>
 __device__ __forceinline__ void mul_acc(Spinor<R>& acc, const cx<R> (&h)[2][3], const Link<R>& U, R scale) {
-  using G = Gamma<MU>;
+  using G = GammaB<MU, BASIS>;
   constexpr int sh = (S < 0) ? 2 : 0;  // multiplying by s = -1 is a factor i^2
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -403,9 +412,9 @@ __device__ __forceinline__ void mul_acc(Spinor<R>& acc, const cx<R> (&h)[2][3], 
 }
 
 // One hop from a decoded neighbour (FP64 / FP32 storage).
-template <int MU, int S, bool DAG_LINK, typename R>
+template <int MU, int S, bool DAG_LINK, int BASIS, typename R>
 __device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const Link<R>& U, R scale) {
-  using G = Gamma<MU>;
+  using G = GammaB<MU, BASIS>;
   constexpr int sh = (S < 0) ? 2 : 0;
   cx<R> h[2][3];
 #pragma unroll
@@ -413,15 +422,15 @@ __device__ __forceinline__ void hop(Spinor<R>& acc, const Spinor<R>& psi, const 
     h[0][c] = psi.v[0][c] + iph<G::PH0 + sh>(psi.v[2 + G::P0][c]);
     h[1][c] = psi.v[1][c] + iph<G::PH1 + sh>(psi.v[2 + G::P1][c]);
   }
-  mul_acc<MU, S, DAG_LINK>(acc, h, U, scale);
+  mul_acc<MU, S, DAG_LINK, BASIS>(acc, h, U, scale);
 }
 
 // One hop from a packed 16-bit neighbour: the projection reads the stored
 // values directly (see proj16), in units of the neighbour's norm.
-template <int MU, int S, bool DAG_LINK, class SF>
+template <int MU, int S, bool DAG_LINK, class SF, int BASIS>
 __device__ __forceinline__ void hop16(Spinor<float>& acc, const Raw16& psi, const Link<float>& U, float scale,
                                       float one) {
-  using G = Gamma<MU>;
+  using G = GammaB<MU, BASIS>;
   constexpr int sh = (S < 0) ? 2 : 0;
   cx<float> h[2][3];
 #pragma unroll
@@ -429,7 +438,75 @@ __device__ __forceinline__ void hop16(Spinor<float>& acc, const Raw16& psi, cons
     h[0][c] = proj16<G::PH0 + sh, SF>(psi.w[c], psi.w[3 * (2 + G::P0) + c], one);
     h[1][c] = proj16<G::PH1 + sh, SF>(psi.w[3 + c], psi.w[3 * (2 + G::P1) + c], one);
   }
-  mul_acc<MU, S, DAG_LINK>(acc, h, U, scale);
+  mul_acc<MU, S, DAG_LINK, BASIS>(acc, h, U, scale);
+}
+
+// ---- temporal hop in the UKQCD basis ---------------------------------------------
+// acc[BASE + k] += scale * W psi[BASE + k] for the two spins the projector keeps
+// (BASE = 0: 1 + gamma_t; BASE = 2: 1 - gamma_t); the factor 2 is in scale.
+template <bool DAG_LINK, int BASE, typename R>
+__device__ __forceinline__ void mul_acc_half(Spinor<R>& acc, const cx<R> (&h)[2][3], const Link<R>& U, R scale) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> w = {R(0), R(0)};
+      if constexpr (!DAG_LINK) {
+        w = cmac(w, U.u[a][0], h[k][0]);
+        w = cmac(w, U.u[a][1], h[k][1]);
+        w = cmac(w, U.u[a][2], h[k][2]);
+      } else {
+        w = cmacc(w, U.u[0][a], h[k][0]);
+        w = cmacc(w, U.u[1][a], h[k][1]);
+        w = cmacc(w, U.u[2][a], h[k][2]);
+      }
+      acc.v[BASE + k][a] = acc.v[BASE + k][a] + scale * w;
+    }
+}
+
+// Spins BASE, BASE + 1 of a neighbour (FP64 / FP32): chunks of one complex
+// (FP64) or two (FP32) hold them contiguously.
+template <class S, int BASE>
+__device__ __forceinline__ void gather_half(const SpinorBuf<S>& b, int i, cx<typename S::real> (&h)[2][3]) {
+  const uint32_t vo = (uint32_t)i * 16u;
+  if constexpr (S::prec == WD_FP64) {
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      const double2 c = __builtin_bit_cast(double2, bload16(b.chunks, vo, (3 * BASE + n) * b.chunk_bytes));
+      h[n / 3][n % 3] = {c.x, c.y};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float4 c = __builtin_bit_cast(float4, bload16(b.chunks, vo, (3 * BASE / 2 + q) * b.chunk_bytes));
+      h[(2 * q) / 3][(2 * q) % 3] = {c.x, c.y};
+      h[(2 * q + 1) / 3][(2 * q + 1) % 3] = {c.z, c.w};
+    }
+  }
+}
+
+// Spins BASE, BASE + 1 of a 16-bit neighbour: 6 packed words (upper: chunk 0
+// and the first half of chunk 1; lower: the second half of chunk 1 and chunk 2).
+template <class S, int BASE>
+__device__ __forceinline__ void gather_half16(const SpinorBuf<S>& b, int i, cx<float> (&h)[2][3], float& scale) {
+  const uint32_t vo = (uint32_t)i * 16u;
+  const float nm = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.norms, (uint32_t)i * 4u, 0, 0));
+  scale = (S::prec == WD_HALF_I16) ? nm * (1.0f / 32767.0f) : nm;
+  uint32_t w[6];
+  if constexpr (BASE == 0) {
+    const uint4 c0 = bload16(b.chunks, vo, 0);
+    const uint2 c1 = bload8(b.chunks, vo, b.chunk_bytes);
+    w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w; w[4] = c1.x; w[5] = c1.y;
+  } else {
+    const uint2 c1 = bload8(b.chunks, vo + 8u, b.chunk_bytes);
+    const uint4 c2 = bload16(b.chunks, vo, 2 * b.chunk_bytes);
+    w[0] = c1.x; w[1] = c1.y; w[2] = c2.x; w[3] = c2.y; w[4] = c2.z; w[5] = c2.w;
+  }
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    if constexpr (S::prec == WD_HALF_I16) h[n / 3][n % 3] = {(float)(int16_t)(w[n] & 0xffffu), (float)(int16_t)(w[n] >> 16)};
+    else h[n / 3][n % 3] = {half_lo(w[n]), half_hi(w[n])};
+  }
 }
 
 // ---- LDS staging of x/y neighbours (16-bit formats) ------------------------------
@@ -509,7 +586,7 @@ __device__ __forceinline__ void lds_gather16(const LdsCtx& c, int k, int sl, Raw
 }
 
 // Both hops of direction MU for the NR right-hand sides of this thread.
-template <class S, int MU, bool DAGGER, int NR, int RECON, bool LDS>
+template <class S, int MU, bool DAGGER, int NR, int RECON, bool LDS, int BASIS>
 __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
                                          const char* __restrict__ links, const SpinorBuf<S> (&in)[NR],
                                          const bool (&on)[NR], int p, int cb, int xh, int row,
@@ -562,17 +639,30 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!on[k]) continue;
-      if constexpr (kHalf<S>) {
+      if constexpr (MU == 3 && BASIS == kBasisUK) {
+        // 1 - gamma_t keeps the lower spins, its adjoint 1 + gamma_t the upper ones
+        constexpr int BASE = DAGGER ? 0 : 2;
+        cx<R> h[2][3];
+        R sc = R(2);
+        if constexpr (kHalf<S>) {
+          float s16;
+          gather_half16<S, BASE>(in[k], nf, h, s16);
+          sc = 2.0f * s16;
+        } else {
+          gather_half<S, BASE>(in[k], nf, h);
+        }
+        mul_acc_half<false, BASE>(acc[k], h, U, flip_f ? -sc : sc);
+      } else if constexpr (kHalf<S>) {
         Raw16 psi;
         float sc;
         if (LDS && lf >= 0) lds_gather16<S>(lc, k, lf, psi, sc);
         else gather_spinor16<S>(in[k], nf, psi, sc);
         if (flip_f) sc = -sc;
-        hop16<MU, DAGGER ? +1 : -1, false, S>(acc[k], psi, U, sc, one);
+        hop16<MU, DAGGER ? +1 : -1, false, S, BASIS>(acc[k], psi, U, sc, one);
       } else {
         Spinor<R> psi;
         gather_spinor<S>(in[k], nf, psi);
-        hop<MU, DAGGER ? +1 : -1, false>(acc[k], psi, U, flip_f ? R(-1) : R(1));
+        hop<MU, DAGGER ? +1 : -1, false, BASIS>(acc[k], psi, U, flip_f ? R(-1) : R(1));
       }
     }
   }
@@ -584,17 +674,30 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!on[k]) continue;
-      if constexpr (kHalf<S>) {
+      if constexpr (MU == 3 && BASIS == kBasisUK) {
+        // 1 + gamma_t keeps the upper spins, its adjoint 1 - gamma_t the lower ones
+        constexpr int BASE = DAGGER ? 2 : 0;
+        cx<R> h[2][3];
+        R sc = R(2);
+        if constexpr (kHalf<S>) {
+          float s16;
+          gather_half16<S, BASE>(in[k], nb, h, s16);
+          sc = 2.0f * s16;
+        } else {
+          gather_half<S, BASE>(in[k], nb, h);
+        }
+        mul_acc_half<true, BASE>(acc[k], h, U, flip_b ? -sc : sc);
+      } else if constexpr (kHalf<S>) {
         Raw16 psi;
         float sc;
         if (LDS && lb >= 0) lds_gather16<S>(lc, k, lb, psi, sc);
         else gather_spinor16<S>(in[k], nb, psi, sc);
         if (flip_b) sc = -sc;
-        hop16<MU, DAGGER ? -1 : +1, true, S>(acc[k], psi, U, sc, one);
+        hop16<MU, DAGGER ? -1 : +1, true, S, BASIS>(acc[k], psi, U, sc, one);
       } else {
         Spinor<R> psi;
         gather_spinor<S>(in[k], nb, psi);
-        hop<MU, DAGGER ? -1 : +1, true>(acc[k], psi, U, flip_b ? R(-1) : R(1));
+        hop<MU, DAGGER ? -1 : +1, true, BASIS>(acc[k], psi, U, flip_b ? R(-1) : R(1));
       }
     }
   }
@@ -606,8 +709,9 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
 //   DOT_OO: |out|^2                  (CG |M p|^2)
 //   DOT_RES: out = y - (x + a * D in), |out|^2 (FP64 residual b_hat - M_hat x)
-// Right-hand sides whose active flag is 0 are skipped.
-template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS>
+// Right-hand sides whose active flag is 0 are skipped.  BASIS: spin basis of
+// in, out, x and y (kBasisDR or kBasisUK); the links do not depend on it.
+template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
                                                        FieldView ys, typename S::real a, int p,
@@ -703,10 +807,10 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     SpinorBuf<S> ib[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0);
-    hop_pair<S, 0, DAGGER, NR, RECON, LDS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
-    hop_pair<S, 1, DAGGER, NR, RECON, LDS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
-    hop_pair<S, 2, DAGGER, NR, RECON, LDS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
-    hop_pair<S, 3, DAGGER, NR, RECON, LDS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_pair<S, 0, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_pair<S, 1, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_pair<S, 2, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_pair<S, 3, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
@@ -846,30 +950,36 @@ static size_t lds_stage_bytes(const DslashGeom& g, int nr) {
   return ((size_t)nr * g.lds_cap * 52 + (size_t)(g.lds_cap / g.Lxh) * 4 + 15) / 16 * 16;
 }
 
-template <class S, bool DAGGER, bool XPAY, int NR, int RECON, bool LDS>
+// The fused dot products serve the solvers, which work in the UKQCD basis;
+// DeGrand-Rossi launches are built without them.
+template <class S, bool DAGGER, bool XPAY, int NR, int RECON, bool LDS, int BASIS>
 static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
                        const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
                        typename S::real a, int p, const int* active, double* partials) {
-  switch (dot) {
-    case DOT_YO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    case DOT_OX:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    case DOT_OO:
-      dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    case DOT_RES:
-      if constexpr (S::prec == WD_FP64 && XPAY && !DAGGER && !LDS)
-        dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
-      break;
-    default:
-      dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+  if constexpr (BASIS == kBasisDR) {
+    dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+  } else {
+    switch (dot) {
+      case DOT_YO:
+        dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        break;
+      case DOT_OX:
+        dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        break;
+      case DOT_OO:
+        dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        break;
+      case DOT_RES:
+        if constexpr (S::prec == WD_FP64 && XPAY && !DAGGER && !LDS)
+          dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        break;
+      default:
+        dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+    }
   }
 }
 
-template <class S, int NR, int RECON, bool LDS>
+template <class S, int NR, int RECON, bool LDS, int BASIS>
 static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
   LaunchCfg c = cfg;
   c.nr = NR;  // the RHS slots of the kernel actually launched
@@ -884,11 +994,11 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   size_t lds = lds_for(c.wgs);
   if constexpr (LDS) lds = std::max(lds, lds_stage_bytes(g, NR));
   if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, true, false, NR, RECON, LDS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, true, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   } else {
-    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, false, false, NR, RECON, LDS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    else launch_dot<S, false, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
   }
 }
 
@@ -909,23 +1019,23 @@ static bool lds_usable(const wd_gauge* gg, wd_prec prec, const LaunchCfg& c) {
   return lds_stage_bytes(g, nr) <= 63488;
 }
 
-template <class S>
+template <class S, int BASIS>
 static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
   if (gg->recon == 8) {
-    launch_nr<S, 2, 8, false>(gg, d, c, s);
+    launch_nr<S, 2, 8, false, BASIS>(gg, d, c, s);
     return;
   }
   if constexpr (kHalf<S>) {
     if (lds_usable(gg, S::prec, c)) {
-      if (c.nr == 3) launch_nr<S, 3, 12, true>(gg, d, c, s);
-      else launch_nr<S, 2, 12, true>(gg, d, c, s);
+      if (c.nr == 3) launch_nr<S, 3, 12, true, BASIS>(gg, d, c, s);
+      else launch_nr<S, 2, 12, true, BASIS>(gg, d, c, s);
       return;
     }
   }
   switch (c.nr) {
-    case 3: launch_nr<S, 3, 12, false>(gg, d, c, s); break;
-    case 4: launch_nr<S, 4, 12, false>(gg, d, c, s); break;
-    default: launch_nr<S, 2, 12, false>(gg, d, c, s); break;
+    case 3: launch_nr<S, 3, 12, false, BASIS>(gg, d, c, s); break;
+    case 4: launch_nr<S, 4, 12, false, BASIS>(gg, d, c, s); break;
+    default: launch_nr<S, 2, 12, false, BASIS>(gg, d, c, s); break;
   }
 }
 

@@ -77,8 +77,8 @@ __global__ void gauge_encode_kernel(SiteMap m, const double* __restrict__ U, int
       uint32_t w[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        w[j] = (uint32_t)f_to_h16((float)v[4 * k + 2 * j]) |
-               ((uint32_t)f_to_h16((float)v[4 * k + 2 * j + 1]) << 16);
+        w[j] = (uint32_t)f_to_h16(pin_f32((float)v[4 * k + 2 * j])) |
+               ((uint32_t)f_to_h16(pin_f32((float)v[4 * k + 2 * j + 1])) << 16);
       reinterpret_cast<uint2*>(const_cast<char*>(link_chunk<SF16>(h16, stride, par, mu, k)))[cb] =
           make_uint2(w[0], w[1]);
     }
@@ -96,12 +96,35 @@ hipError_t launch_gauge_encode(const wd_gauge* g, const double* U, hipStream_t s
 }
 
 // ---- spinors ----------------------------------------------------------------------
+// Change of spin basis in FP64 (Appendix B), v = [spin][colour][re, im]:
+// to_uk: v <- S v with S = [[0, 1, 0, 1], [-1, 0, -1, 0], [0, 1, 0, -1],
+// [-1, 0, 1, 0]] / sqrt(2) (DeGrand-Rossi to UKQCD); otherwise v <- S^T v.
+__device__ __forceinline__ void change_basis(double (&v)[24], bool to_uk) {
+  constexpr double r = 0.70710678118654752440;  // 1 / sqrt(2)
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {  // colour and re / im
+    const double a0 = v[k], a1 = v[6 + k], a2 = v[12 + k], a3 = v[18 + k];
+    if (to_uk) {
+      v[k] = r * (a1 + a3);
+      v[6 + k] = -r * (a0 + a2);
+      v[12 + k] = r * (a1 - a3);
+      v[18 + k] = r * (a2 - a0);
+    } else {
+      v[k] = -r * (a1 + a3);
+      v[6 + k] = r * (a0 + a2);
+      v[12 + k] = r * (a3 - a1);
+      v[18 + k] = r * (a0 - a2);
+    }
+  }
+}
+
 // full_parity < 0: canonical array is a parity array [nrhs][Vh][24];
 // full_parity = p: canonical array is a full lattice [nrhs][V][24] and the
-// field holds its parity-p sites.
+// field holds its parity-p sites.  The canonical array is in the
+// DeGrand-Rossi basis, the field in `basis`.
 template <class S>
 __global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __restrict__ canon,
-                                     int full_parity) {
+                                     int full_parity, int basis) {
   using R = typename S::real;
   const int cb = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -109,15 +132,19 @@ __global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __res
   const int64_t V = 2 * (int64_t)m.Vh;
   const double* src = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
                                         : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
+  double v[24];
+#pragma unroll
+  for (int n = 0; n < 24; ++n) v[n] = src[n];
+  if (basis == kBasisUK) change_basis(v, true);
   Spinor<R> s;
 #pragma unroll
-  for (int n = 0; n < 12; ++n) s.v[n / 3][n % 3] = {static_cast<R>(src[2 * n]), static_cast<R>(src[2 * n + 1])};
+  for (int n = 0; n < 12; ++n) s.v[n / 3][n % 3] = {static_cast<R>(v[2 * n]), static_cast<R>(v[2 * n + 1])};
   store_spinor<S>(f, r, cb, s);
 }
 
 template <class S>
 __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict__ canon,
-                                     int full_parity) {
+                                     int full_parity, int basis) {
   using R = typename S::real;
   const int cb = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -127,61 +154,69 @@ __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict_
                                   : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
   Spinor<R> s;
   load_spinor<S>(f, r, cb, s);
+  double v[24];
 #pragma unroll
   for (int n = 0; n < 12; ++n) {
-    dst[2 * n] = static_cast<double>(s.v[n / 3][n % 3].re);
-    dst[2 * n + 1] = static_cast<double>(s.v[n / 3][n % 3].im);
+    v[2 * n] = static_cast<double>(s.v[n / 3][n % 3].re);
+    v[2 * n + 1] = static_cast<double>(s.v[n / 3][n % 3].im);
   }
+  if (basis == kBasisUK) change_basis(v, false);
+#pragma unroll
+  for (int n = 0; n < 24; ++n) dst[n] = v[n];
 }
 
 template <class S>
-static hipError_t enc_typed(const Geom& g, Field f, const double* canon, int full_parity,
+static hipError_t enc_typed(const Geom& g, Field f, const double* canon, int full_parity, int basis,
                             hipStream_t s) {
   const int block = 256;
   dim3 grid((g.Vh + block - 1) / block, f.nrhs);
   spinor_encode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
-                                                 canon, full_parity);
+                                                 canon, full_parity, basis);
   return hipGetLastError();
 }
 
 template <class S>
-static hipError_t dec_typed(const Geom& g, double* canon, Field f, int full_parity, hipStream_t s) {
+static hipError_t dec_typed(const Geom& g, double* canon, Field f, int full_parity, int basis,
+                            hipStream_t s) {
   const int block = 256;
   dim3 grid((g.Vh + block - 1) / block, f.nrhs);
   spinor_decode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
-                                                 canon, full_parity);
+                                                 canon, full_parity, basis);
   return hipGetLastError();
 }
 
 hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
-                                    int full_parity, hipStream_t s) {
+                                    int full_parity, hipStream_t s, int basis) {
+  if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
   switch (p) {
-    case WD_FP64: return enc_typed<SF64>(g, f, canon, full_parity, s);
-    case WD_FP32: return enc_typed<SF32>(g, f, canon, full_parity, s);
-    case WD_HALF_I16: return enc_typed<SI16>(g, f, canon, full_parity, s);
-    case WD_HALF_F16: return enc_typed<SF16>(g, f, canon, full_parity, s);
+    case WD_FP64: return enc_typed<SF64>(g, f, canon, full_parity, basis, s);
+    case WD_FP32: return enc_typed<SF32>(g, f, canon, full_parity, basis, s);
+    case WD_HALF_I16: return enc_typed<SI16>(g, f, canon, full_parity, basis, s);
+    case WD_HALF_F16: return enc_typed<SF16>(g, f, canon, full_parity, basis, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
-                                    int full_parity, hipStream_t s) {
+                                    int full_parity, hipStream_t s, int basis) {
+  if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
   switch (p) {
-    case WD_FP64: return dec_typed<SF64>(g, canon, f, full_parity, s);
-    case WD_FP32: return dec_typed<SF32>(g, canon, f, full_parity, s);
-    case WD_HALF_I16: return dec_typed<SI16>(g, canon, f, full_parity, s);
-    case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, s);
+    case WD_FP64: return dec_typed<SF64>(g, canon, f, full_parity, basis, s);
+    case WD_FP32: return dec_typed<SF32>(g, canon, f, full_parity, basis, s);
+    case WD_HALF_I16: return dec_typed<SI16>(g, canon, f, full_parity, basis, s);
+    case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, basis, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,
-                                hipStream_t s) {
-  return launch_spinor_encode_map(g, p, f, canon, -1, s);
+                                hipStream_t s, int basis) {
+  return launch_spinor_encode_map(g, p, f, canon, -1, s, basis);
 }
 
-hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f, hipStream_t s) {
-  return launch_spinor_decode_map(g, p, canon, f, -1, s);
+hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f, hipStream_t s,
+                                int basis) {
+  return launch_spinor_decode_map(g, p, canon, f, -1, s, basis);
 }
 
 }  // namespace wd

@@ -105,7 +105,7 @@ __global__ void gauge_encode8_kernel(Lat m, const double* __restrict__ U, int64_
   if (h16) {
     uint32_t q[4];
     for (int j = 0; j < 4; ++j)
-      q[j] = (uint32_t)f_to_h16((float)w[2 * j]) | ((uint32_t)f_to_h16((float)w[2 * j + 1]) << 16);
+      q[j] = (uint32_t)f_to_h16(pin_f32((float)w[2 * j])) | ((uint32_t)f_to_h16(pin_f32((float)w[2 * j + 1])) << 16);
     reinterpret_cast<uint4*>(h16 + (chunk * stride) * 16)[cb] = make_uint4(q[0], q[1], q[2], q[3]);
   }
 }

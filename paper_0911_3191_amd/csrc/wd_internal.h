@@ -68,6 +68,10 @@ enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4 };
 // out = *xpay + a * D in; with xpay and dot set, per-block FP64 partials of
 // the dot products named by DotMode go to partials[rhs][block][4].  RHS whose
 // active flag is 0 are skipped.
+// Spin bases of spinor fields (Appendix B): the caller's fields are in the
+// DeGrand-Rossi basis, the solvers rotate theirs into the UKQCD basis.
+constexpr int kBasisDR = 0, kBasisUK = 1;
+
 struct DslashArgs {
   Field out{}, in{};
   int out_parity = 0, dagger = 0;
@@ -77,6 +81,7 @@ struct DslashArgs {
   const Field* y = nullptr;
   double* partials = nullptr;
   const int* active = nullptr;
+  int basis = kBasisDR;  // spin basis of the fields (fused dots: UKQCD only)
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 
@@ -102,12 +107,13 @@ int dslash_partial_blocks(const Geom& geo, int nrhs, const LaunchCfg& c);
 // stream is being captured.
 LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 // Runs the tuner for (prec, nrhs) on the given fields (out = D in is computed).
-void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, hipStream_t s);
+void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int basis, hipStream_t s);
 
 // out_p = D_{p,1-p} in (dagger: adjoint).  When xpay_src is non-null:
 // out = xpay_src + a * D in (xpay_src has parity p, same precision).
 hipError_t launch_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int out_parity,
-                         int dagger, const Field* xpay_src, double a, hipStream_t s);
+                         int dagger, const Field* xpay_src, double a, hipStream_t s,
+                         int basis = kBasisDR);
 
 hipError_t launch_gauge_encode(const wd_gauge* g, const double* U, hipStream_t s);
 // 8-real links, temporal gauge (wd_gauge.hip)
@@ -117,17 +123,18 @@ hipError_t launch_gauge_fix_temporal(const Geom& geo, const double* U, double* U
 hipError_t launch_gauge_rotate(const Geom& geo, const double* g, const double* in, double* out, int nrhs,
                                int adjoint, hipStream_t s);
 
-// canonical parity spinors [nrhs][Vh][24] <-> field
+// canonical parity spinors [nrhs][Vh][24] (DeGrand-Rossi basis) <-> field
+// (spin basis `basis`)
 hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,
-                                hipStream_t s);
+                                hipStream_t s, int basis = kBasisDR);
 hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f,
-                                hipStream_t s);
+                                hipStream_t s, int basis = kBasisDR);
 // full_parity = p: the canonical array is a full lattice [nrhs][V][24] and the
 // field holds (or provides) its parity-p sites; full_parity < 0: parity array.
 hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
-                                    int full_parity, hipStream_t s);
+                                    int full_parity, hipStream_t s, int basis = kBasisDR);
 hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
-                                    int full_parity, hipStream_t s);
+                                    int full_parity, hipStream_t s, int basis = kBasisDR);
 
 // ---- solver state on the device --------------------------------------------------
 // Per-RHS FP64 scalars (complex ones take two slots: re, im).

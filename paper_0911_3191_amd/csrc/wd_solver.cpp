@@ -102,6 +102,7 @@ static hipError_t dslash_into(wd_solver* h, wd_prec prec, const Field& out, cons
   d.y = y;
   d.partials = h->partials;
   d.active = mask;
+  d.basis = kBasisUK;
   return launch_dslash_ex(h->g, prec, d, h->s);
 }
 
@@ -220,9 +221,11 @@ static hipError_t prepare(wd_solver* h) {
   const Geom& g = h->geom;
   const int n = h->nrhs;
   WD_TRY(solver_init_flags(n, h->fl, h->active, h->rumask, h->s));
-  // b_e -> r, b_o -> to64; |b|^2 = |b_e|^2 + |b_o|^2
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s));
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s));
+  // b_e -> r, b_o -> to64, rotated into the UKQCD basis every solver field
+  // uses (S is orthogonal: norms and inner products are those of the caller's
+  // basis); |b|^2 = |b_e|^2 + |b_o|^2
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK));
   WD_TRY(blas_norm2(g, WD_FP64, h->r, nullptr, h->partials, h->s));
   WD_TRY(fin(h, FIN_B2_FIRST, nullptr));
   WD_TRY(blas_norm2(g, WD_FP64, h->to64, nullptr, h->partials, h->s));
@@ -241,14 +244,15 @@ static hipError_t prepare(wd_solver* h) {
   return hipSuccess;
 }
 
-// x_o = b_o + kappa D_oe x_e, then both parities into the caller's x.
+// x_o = b_o + kappa D_oe x_e, then both parities into the caller's x (back in
+// the DeGrand-Rossi basis).
 static hipError_t reconstruct(wd_solver* h) {
   const Geom& g = h->geom;
   WD_TRY(blas_scale_bnorm(g, h->x, h->sc, 0, h->s));  // undo the unit-source scaling
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK));
   WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, &h->to64, h->kappa, DOT_NONE, nullptr, nullptr));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s, kBasisUK));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s, kBasisUK));
   return hipStreamSynchronize(h->s);
 }
 
@@ -368,7 +372,7 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   e = prepare(h);  // its FP64 dslash launches pick their own launch shape
   // pick the inner-precision launch shape before any graph capture, on
   // (p -> odd temporary); the temporary is scratch at this point
-  if (e == hipSuccess) tune_dslash(g, prm->inner, h->to, h->p, h->s);
+  if (e == hipSuccess) tune_dslash(g, prm->inner, h->to, h->p, kBasisUK, h->s);
   if (e == hipSuccess) e = read_flags(h);
   if (e != hipSuccess) {
     (void)hipHostFree(h->h_fl);

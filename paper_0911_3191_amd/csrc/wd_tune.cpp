@@ -11,7 +11,7 @@
 // tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
 // across processes (one "Lx Ly Lz Lt prec nrhs flags nr block gslow nsub
 // link_nt lds" line per entry, flags = 1 for 8-real links + 2 for temporal
-// gauge); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
+// gauge + 4 for UKQCD-basis fields); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
 // WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs[,lds]]]]" forces a shape
 // (the RHS-group-slowest order, streaming output stores and the occupancy
 // cap are not searched: none paid on the lattices measured).
@@ -30,16 +30,16 @@ namespace wd {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int>;  // dims, prec, nrhs, link flags
+using Key = std::tuple<int, int, int, int, int, int>;  // dims, prec, nrhs, link and basis flags
 
 std::mutex g_mu;
 std::map<Key, LaunchCfg> g_cache;
 bool g_loaded = false;
 
-Key key_of(const wd_gauge* g, wd_prec prec, int nrhs) {
+Key key_of(const wd_gauge* g, wd_prec prec, int nrhs, int basis) {
   const Geom& geo = g->geom;
   return Key{geo.L[0], geo.L[1], geo.L[2], geo.L[3] * 8 + static_cast<int>(prec), nrhs,
-             (g->recon == 8 ? 1 : 0) | (g->tgauge ? 2 : 0)};
+             (g->recon == 8 ? 1 : 0) | (g->tgauge ? 2 : 0) | (basis == kBasisUK ? 4 : 0)};
 }
 
 LaunchCfg default_cfg(wd_prec, int) { return LaunchCfg{2, 256}; }
@@ -166,7 +166,7 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
         (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8 && (lds == 0 || lds == 1))
       return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs, lds};
   }
-  const Key k = key_of(g, prec, nrhs);
+  const Key k = key_of(g, prec, nrhs, d.basis);
   {
     std::lock_guard<std::mutex> lock(g_mu);
     load_cache_locked();
@@ -185,11 +185,12 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
   return best;
 }
 
-void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, hipStream_t s) {
+void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int basis, hipStream_t s) {
   DslashArgs d;
   d.out = out;
   d.in = in;
   d.out_parity = 1;
+  d.basis = basis;
   (void)tuned_dslash_config(g, prec, d, s);
 }
 

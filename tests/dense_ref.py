@@ -16,6 +16,10 @@ from golden_io import read_projectors
 
 PROJ = read_projectors("projectors_degrand_rossi.txt")
 
+# Change of basis psi_UK = S psi_DR between the two printed tables of
+# Appendix B (checked against both tables by the oracle pins).
+UKQCD_S = np.array([[0, 1, 0, 1], [-1, 0, -1, 0], [0, 1, 0, -1], [-1, 0, 1, 0]]) / np.sqrt(2)
+
 
 def gammas(proj=PROJ):
     """gamma_mu = (P^{+mu} - P^{-mu}) / 2 for mu = 1..4 (list index 0..3)."""

@@ -30,16 +30,16 @@ class Setup:
         torch.cuda.synchronize()
         return f
 
-    def encode_parity(self, prec, psi_par, nrhs=1):
+    def encode_parity(self, prec, psi_par, nrhs=1, basis=0):
         f = self.field(prec, nrhs)
         canon = torch.from_numpy(np.ascontiguousarray(psi_par, dtype=np.float64)).to(DEV)
-        wd.wd_spinor_encode(self.lat, prec, nrhs, f, canon)
+        wd.wd_spinor_encode_basis(self.lat, prec, nrhs, basis, f, canon)
         torch.cuda.synchronize()
         return f
 
-    def decode(self, prec, f, nrhs=1):
+    def decode(self, prec, f, nrhs=1, basis=0):
         out = torch.zeros(nrhs * self.Vh * 24, dtype=torch.float64, device=DEV)
-        wd.wd_spinor_decode(self.lat, prec, nrhs, out, f)
+        wd.wd_spinor_decode_basis(self.lat, prec, nrhs, basis, out, f)
         torch.cuda.synchronize()
         a = out.cpu().numpy().reshape(nrhs, self.Vh, 4, 3, 2)
         return a[0] if nrhs == 1 else a

@@ -25,7 +25,8 @@ def lib():
 
 def test_header_declares_the_path_entry_points():
     names = declared_functions()
-    for n in ("wilson_dslash", "mdagm", "wilson_mat_pc", "wd_gauge_create", "wd_spinor_encode"):
+    for n in ("wilson_dslash", "mdagm", "wilson_mat_pc", "wd_gauge_create", "wd_spinor_encode",
+              "wilson_dslash_basis", "wd_spinor_encode_basis", "wd_spinor_decode_basis"):
         assert n in names
 
 
@@ -58,6 +59,12 @@ def test_validation_rejects_bad_lattices_and_arguments(lib):
     bad = wd.lattice((4, 4, 4, 5))
     st = lib.wd_spinor_encode(ctypes.byref(bad), 0, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
     assert st == -1 and b"even" in lib.wd_last_error()
+    # an unknown spin basis is refused before any launch
+    for fn in (lib.wd_spinor_encode_basis, lib.wd_spinor_decode_basis):
+        st = fn(ctypes.byref(lat), 0, 1, 2, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+        assert st == -1 and b"basis" in lib.wd_last_error()
+    st = lib.wilson_dslash_basis(None, None, None, 0, 0, 0, 1, 1, None)
+    assert st == -1 and b"NULL" in lib.wd_last_error()
 
 
 @pytest.mark.parametrize("field,value,msg", [

@@ -139,18 +139,15 @@ def test_spinor16_encode_is_bit_exact_with_oracle(kind):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("kind", ["i16", "f16"])
-def test_16bit_dslash_against_oracle_on_quantised_inputs(kind):
+def check_on_quantised_inputs(kind, dims, U, seed):
     """Feed the oracle the 16-bit-rounded links and spinor: what remains is FP32
     arithmetic plus one output rounding, bounded per site by the output norm."""
-    dims = (6, 4, 6, 10)
-    U = wdinputs.gauge_random(dims, 0.5, 41)
     s = Setup(dims, U)
     Uq = oracle.decode_link16(kind, oracle.encode_link16(kind, U))
     uq = Uq[..., 0] + 1j * Uq[..., 1]
     c = np.conj(np.cross(uq[..., 0, :], uq[..., 1, :]))  # the third row the kernel rebuilds
     Uq[..., 2, :, 0], Uq[..., 2, :, 1] = c.real, c.imag
-    psi = wdinputs.spinor_gaussian(dims, 42)
+    psi = wdinputs.spinor_gaussian(dims, seed)
     _, po = oracle.split(dims, psi)
     q, nm = oracle.encode_spinor16(kind, po)
     po_q = oracle.decode_spinor16(kind, q, nm)
@@ -166,6 +163,26 @@ def test_16bit_dslash_against_oracle_on_quantised_inputs(kind):
     i, j = np.unravel_index(np.argmax(ratio), ratio.shape)
     assert ratio.max() <= 1.0, (f"site {i} comp {j}: got {got[i, j]!r} ref {ref[i, j]!r} "
                                 f"norm {site_norm[i, 0]!r} ratio {ratio.max():.3f}")
+
+
+@pytest.mark.parametrize("kind", ["i16", "f16"])
+def test_16bit_dslash_against_oracle_on_quantised_inputs(kind):
+    dims = (6, 4, 6, 10)
+    check_on_quantised_inputs(kind, dims, wdinputs.gauge_random(dims, 0.5, 41), 42)
+
+
+def test_binary16_links_round_through_binary32():
+    """A link real just above a binary16 rounding tie that binary32 rounding
+    lands on exactly: binary32 first (the format's definition) rounds the tie
+    to even, a direct FP64 -> binary16 rounding goes up.  Every link carries
+    one such real, so the two roundings disagree on every link."""
+    dims = (6, 4, 6, 10)
+    U = wdinputs.gauge_random(dims, 0.5, 43)
+    tie = 2457 / 8192          # halfway between the binary16 values 1228/4096 and 1229/4096
+    v = tie + 2.0 ** -27       # below half a binary32 ulp above the tie
+    assert np.float16(np.float32(v)) != np.float16(v)
+    U[..., 0, 0, 0] = v
+    check_on_quantised_inputs("f16", dims, U, 44)
 
 
 def test_accuracy_cdf_uniform_vector():

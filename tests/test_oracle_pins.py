@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import wdinputs
-from dense_ref import PROJ, dense_hopping, enumerate_sites, from_vec, gammas, parity_masks, to_vec
+from dense_ref import PROJ, UKQCD_S, dense_hopping, enumerate_sites, from_vec, gammas, parity_masks, to_vec
 from golden_io import read_projectors
 
 TINY = [(2, 2, 2, 2), (2, 4, 2, 6), (4, 2, 2, 4)]
@@ -89,7 +89,7 @@ def test_ukqcd_table_is_a_valid_basis_change_of_the_degrand_rossi_table():
         for b in range(4):
             assert np.allclose(gu[a] @ gu[b] + gu[b] @ gu[a], 2 * (a == b) * np.eye(4))
     assert np.allclose(gu[3], np.diag([1, 1, -1, -1]))
-    S = np.array([[0, 1, 0, 1], [-1, 0, -1, 0], [0, 1, 0, -1], [-1, 0, 1, 0]]) / np.sqrt(2)
+    S = UKQCD_S
     assert np.allclose(S @ S.conj().T, np.eye(4))
     for a in range(4):
         assert np.allclose(S @ gd[a] @ S.conj().T, gu[a])
