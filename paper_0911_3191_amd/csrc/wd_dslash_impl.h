@@ -89,7 +89,8 @@ struct DslashGeom {
   FastDiv div_sub_plane;  // / sub_plane
   int site_blocks;      // site blocks per XCD (slab) or in total (contiguous)
   int ngroups;          // RHS groups
-  int nrhs;
+  int nrhs;             // RHS the launch covers (entries of the RHS list when mapped)
+  int mapped;           // 1: `sel` lists the RHS indices to process; 0: it is an active mask (or null)
   int gslow;            // 1: an XCD sweeps its slab once per RHS group (group slowest)
   int link_nt;          // 1: link loads are marked streaming (read once per launch)
   int out_nt;           // 1: output stores are marked streaming
@@ -709,13 +710,15 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
 //   DOT_OO: |out|^2                  (CG |M p|^2)
 //   DOT_RES: out = y - (x + a * D in), |out|^2 (FP64 residual b_hat - M_hat x)
-// Right-hand sides whose active flag is 0 are skipped.  BASIS: spin basis of
-// in, out, x and y (kBasisDR or kBasisUK); the links do not depend on it.
+// Right-hand sides whose active flag in `sel` is 0 are skipped; with g.mapped,
+// `sel` instead lists the g.nrhs right-hand sides to process, packed into the
+// RHS slots of as few groups as they fill.  BASIS: spin basis of in, out, x
+// and y (kBasisDR or kBasisUK); the links do not depend on it.
 template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
                                                        FieldView ys, typename S::real a, int p,
-                                                       const int* __restrict__ active,
+                                                       const int* __restrict__ sel,
                                                        double* __restrict__ partials) {
   using R = typename S::real;
   // ---- which sites and RHS this workgroup owns ----
@@ -769,8 +772,14 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
   bool any = false;
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
-    rhs[k] = group * NR + k;
-    on[k] = rhs[k] < g.nrhs && (!active || active[rhs[k]]);
+    const int slot = group * NR + k;
+    if (g.mapped) {
+      on[k] = slot < g.nrhs;
+      rhs[k] = on[k] ? sel[slot] : 0;
+    } else {
+      rhs[k] = slot;
+      on[k] = slot < g.nrhs && (!sel || sel[slot]);
+    }
     any |= on[k];
   }
   if (!any) return;
@@ -903,6 +912,7 @@ static DslashGeom make_dgeom(const Geom& geo, int nrhs, const LaunchCfg& c) {
   g.div_ly = make_fastdiv(geo.L[1]);
   g.div_lz = make_fastdiv(geo.L[2]);
   g.nrhs = nrhs;
+  g.mapped = 0;
   g.ngroups = (nrhs + c.nr - 1) / c.nr;
   g.gslow = c.gslow;
   g.link_nt = c.link_nt;
@@ -955,26 +965,26 @@ static size_t lds_stage_bytes(const DslashGeom& g, int nr) {
 template <class S, bool DAGGER, bool XPAY, int NR, int RECON, bool LDS, int BASIS>
 static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
                        const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
-                       typename S::real a, int p, const int* active, double* partials) {
+                       typename S::real a, int p, const int* sel, double* partials) {
   if constexpr (BASIS == kBasisDR) {
-    dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+    dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
   } else {
     switch (dot) {
       case DOT_YO:
-        dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
         break;
       case DOT_OX:
-        dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
         break;
       case DOT_OO:
-        dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
         break;
       case DOT_RES:
         if constexpr (S::prec == WD_FP64 && XPAY && !DAGGER && !LDS)
-          dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+          dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
         break;
       default:
-        dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, active, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
     }
   }
 }
@@ -983,7 +993,8 @@ template <class S, int NR, int RECON, bool LDS, int BASIS>
 static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
   LaunchCfg c = cfg;
   c.nr = NR;  // the RHS slots of the kernel actually launched
-  DslashGeom g = make_dgeom(gg->geom, d.out.nrhs, c);
+  DslashGeom g = make_dgeom(gg->geom, d.rhs_map ? d.n_map : d.out.nrhs, c);
+  g.mapped = d.rhs_map ? 1 : 0;
   g.tgauge = gg->tgauge;
   const char* links = static_cast<const char*>(gg->link[S::prec]);
   const unsigned grid = grid_blocks(g);
@@ -994,11 +1005,11 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   size_t lds = lds_for(c.wgs);
   if constexpr (LDS) lds = std::max(lds, lds_stage_bytes(g, NR));
   if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, true, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
+    else launch_dot<S, true, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
   } else {
-    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
-    else launch_dot<S, false, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.active, d.partials);
+    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
+    else launch_dot<S, false, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
   }
 }
 

@@ -80,7 +80,11 @@ struct DslashArgs {
   int dot = DOT_NONE;
   const Field* y = nullptr;
   double* partials = nullptr;
-  const int* active = nullptr;
+  const int* active = nullptr;  // device mask [nrhs]: RHS with 0 are skipped
+  // Device list of n_map RHS indices (distinct, < out.nrhs): only those are
+  // processed, packed into as few RHS groups as they fill (replaces `active`).
+  const int* rhs_map = nullptr;
+  int n_map = 0;
   int basis = kBasisDR;  // spin basis of the fields (fused dots: UKQCD only)
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);

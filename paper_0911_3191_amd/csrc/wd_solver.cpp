@@ -49,7 +49,7 @@ static Layout layout(const Geom& g, int kind, wd_prec inner, int nrhs) {
   L.partials = align256(sizeof(double) * kMaxDotHost * nb * (size_t)nrhs);
   L.scalars = align256(sizeof(double) * SC_COUNT * (size_t)nrhs);
   L.flags = align256(sizeof(int) * FL_COUNT * (size_t)nrhs);
-  L.masks = align256(sizeof(int) * 2 * (size_t)nrhs);
+  L.masks = align256(sizeof(int) * 3 * (size_t)nrhs);  // active, rumask, the list of updating RHS
   L.total = (L.n_hi_even + L.n_hi_odd) * L.hi_field + (L.n_lo_even + L.n_lo_odd) * L.lo_field +
             L.partials + L.scalars + L.flags + L.masks;
   return L;
@@ -74,7 +74,9 @@ struct wd_solver {
   int* fl;
   int* active;
   int* rumask;
+  int* rumap;      // the RHS of a reliable update, listed (device)
   int* h_fl;       // pinned host copy of the flags
+  int* h_map;      // pinned host staging of rumap (after the flags in the same buffer)
   double* h_sc;    // pinned host copy of the scalars
   std::vector<int> iters, rus, status, done_rhs;
   std::string note;  // breakdown details for wd_last_error
@@ -155,11 +157,32 @@ static hipError_t iteration_body(wd_solver* h) {
   return hipSuccess;
 }
 
-// FP64 r = b_hat - M_hat x for the RHS in mask, then the convergence test.
-// The subtraction from b_hat and |r|^2 are fused into the second dslash.
-static hipError_t true_residual(wd_solver* h, const int* mask) {
-  WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, nullptr, 0.0, DOT_NONE, nullptr, mask));
-  WD_TRY(dslash_into(h, WD_FP64, h->r, h->to64, 0, 0, &h->x, -h->kappa * h->kappa, DOT_RES, &h->bhat, mask));
+// FP64 r = b_hat - M_hat x for the RHS in mask (all when null), then the
+// convergence test.  The subtraction from b_hat and |r|^2 are fused into the
+// second dslash.  With n_map > 0 the dslash launches cover only the n_map RHS
+// listed in h->rumap (the same set as mask), packed into as few RHS groups as
+// they fill, rather than the whole batch with most of it masked off.
+static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0) {
+  DslashArgs d;
+  d.out = h->to64;
+  d.in = h->x;
+  d.out_parity = 1;
+  d.partials = h->partials;
+  d.active = mask;
+  d.basis = kBasisUK;
+  if (n_map > 0) {
+    d.rhs_map = h->rumap;
+    d.n_map = n_map;
+  }
+  WD_TRY(launch_dslash_ex(h->g, WD_FP64, d, h->s));
+  d.out = h->r;
+  d.in = h->to64;
+  d.out_parity = 0;
+  d.xpay = &h->x;
+  d.a = -h->kappa * h->kappa;
+  d.dot = DOT_RES;
+  d.y = &h->bhat;
+  WD_TRY(launch_dslash_ex(h->g, WD_FP64, d, h->s));
   WD_TRY(fin(h, FIN_TRUE, mask));
   return hipSuccess;
 }
@@ -192,8 +215,16 @@ static hipError_t reseed(wd_solver* h, bool first) {
 }
 
 static hipError_t reliable_update(wd_solver* h) {
+  // the RHS that flagged an update (the device's rumask), listed for the dslash
+  int n = 0;
+  for (int k = 0; k < h->nrhs; ++k)
+    if (!h->done_rhs[k] && h->h_fl[k * FL_COUNT + FL_RU]) h->h_map[n++] = k;
+  if (n > 0 && n < h->nrhs)
+    WD_TRY(hipMemcpyAsync(h->rumap, h->h_map, sizeof(int) * n, hipMemcpyHostToDevice, h->s));
+  else
+    n = 0;  // every RHS (or, defensively, none listed): the mask alone
   WD_TRY(blas_accum(h->geom, h->prm.inner, h->x, h->xh, h->rumask, h->s));  // x += x^
-  WD_TRY(true_residual(h, h->rumask));                                       // r = b - M x
+  WD_TRY(true_residual(h, h->rumask, n));                                    // r = b - M x
   WD_TRY(reseed(h, false));                                                  // r^ = r, x^ = 0
   return hipSuccess;
 }
@@ -354,6 +385,7 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   p += L.flags;
   h->active = reinterpret_cast<int*>(p);
   h->rumask = h->active + h->nrhs;
+  h->rumap = h->rumask + h->nrhs;
   h->iters.assign(h->nrhs, 0);
   h->rus.assign(h->nrhs, 0);
   h->status.assign(h->nrhs, WD_NOT_CONVERGED);
@@ -362,7 +394,8 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   h->finished = false;
   h->loops = 0;
   h->t0 = std::chrono::steady_clock::now();
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->h_fl), sizeof(int) * FL_COUNT * h->nrhs);
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->h_fl), sizeof(int) * (FL_COUNT + 1) * h->nrhs);
+  h->h_map = h->h_fl + FL_COUNT * h->nrhs;
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&h->h_sc), sizeof(double) * SC_COUNT * h->nrhs);
   if (e != hipSuccess) {

@@ -178,6 +178,7 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return default_cfg(prec, nrhs);
   if (d.xpay && d.xpay->ptr == d.out.ptr) return default_cfg(prec, nrhs);
+  if (d.rhs_map) return default_cfg(prec, nrhs);  // a launch over part of the batch does not tune
   const LaunchCfg best = run_tuner(g, prec, d, s);
   std::lock_guard<std::mutex> lock(g_mu);
   g_cache[k] = best;
