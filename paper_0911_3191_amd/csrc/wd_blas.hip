@@ -327,8 +327,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
                                                      const int* __restrict__ mask, FinArgs fa) {
   const int rhs = blockIdx.x;
   if (mask && !mask[rhs]) return;
-  double v[3];
-  sum_partials<3>(partials + (int64_t)rhs * nb * kMaxDot, nb, v);
+  double v[4];  // component 3: FIN_TRUE_RHO only (other stages leave it unset)
+  sum_partials<4>(partials + (int64_t)rhs * nb * kMaxDot, nb, v);
   if (threadIdx.x != 0) return;
   double* s = sc + rhs * SC_COUNT;
   int* f = fl + rhs * FL_COUNT;
@@ -355,6 +355,20 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       s[SC_R2] = v[0];
       s[SC_RHO] = v[1];
       s[SC_RHO + 1] = v[2];
+      break;
+    }
+    case FIN_TRUE_RHO: {  // both, from the residual dslash that re-encoded r itself
+      s[SC_RTRUE2] = v[0];
+      s[SC_MMAX] = sqrt(v[0]);
+      f[FL_CONV] = (sqrt(v[0]) <= stop) ? 1 : 0;
+      if (!isfinite(v[0])) f[FL_BREAK] = FIN_TRUE + 1;
+      if (f[FL_CONV] || f[FL_BREAK]) active[rhs] = 0;
+      rumask[rhs] = active[rhs];
+      if (active[rhs]) {
+        s[SC_R2] = v[1];
+        s[SC_RHO] = v[2];
+        s[SC_RHO + 1] = v[3];
+      }
       break;
     }
     case FIN_BICG_INIT: {

@@ -30,6 +30,10 @@ hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d
   if (d.basis == kBasisDR && d.xpay && d.dot != DOT_NONE) return hipErrorInvalidValue;
   if (d.rhs_map && (d.n_map < 1 || d.n_map > d.out.nrhs)) return hipErrorInvalidValue;
   if (d.dot == DOT_RES && (prec != WD_FP64 || !d.xpay || !d.y || d.dagger)) return hipErrorInvalidValue;
+  if (d.dot == DOT_RES_ENC &&
+      (prec != WD_FP64 || !d.xpay || !d.y || d.dagger || d.basis != kBasisUK || !d.enc_rh || !d.enc_xh ||
+       !d.enc_rt || d.enc_prec < WD_FP32 || d.enc_prec > WD_HALF_F16))
+    return hipErrorInvalidValue;
   LaunchCfg c = tuned_dslash_config(g, prec, d, s);
   // A fused dot sums each workgroup's sites into one partial record; with one
   // sub-slab those site sets are fixed whatever nr and gslow are, so the

@@ -710,16 +710,22 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_OX: <out, x>, |out|^2        (BiCGstab <t, s>, <t, t> with x = s)
 //   DOT_OO: |out|^2                  (CG |M p|^2)
 //   DOT_RES: out = y - (x + a * D in), |out|^2 (FP64 residual b_hat - M_hat x)
+//   DOT_RES_ENC: r = y - (x + a * D in) re-encoded in format S2 into enc.rh
+//     (out is not written), enc.xh = 0; |r|^2, |enc(r)|^2, <enc.rt, enc(r)>
 // Right-hand sides whose active flag in `sel` is 0 are skipped; with g.mapped,
 // `sel` instead lists the g.nrhs right-hand sides to process, packed into the
 // RHS slots of as few groups as they fill.  BASIS: spin basis of in, out, x
 // and y (kBasisDR or kBasisUK); the links do not depend on it.
-template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS>
+struct EncView {
+  FieldView rh, xh, rt;
+};
+
+template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS, class S2 = S>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
                                                        FieldView ys, typename S::real a, int p,
                                                        const int* __restrict__ sel,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials, EncView enc) {
   using R = typename S::real;
   // ---- which sites and RHS this workgroup owns ----
   const int xcd = blockIdx.x & 7;
@@ -833,7 +839,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
 #pragma unroll
           for (int c = 0; c < 3; ++c) acc[k].v[s][c] = x.v[s][c] + a * acc[k].v[s][c];
       }
-      if constexpr (DOT == DOT_RES) {
+      if constexpr (DOT == DOT_RES || DOT == DOT_RES_ENC) {
         Spinor<R> b;
         load_spinor<S>(ys, rhs[k], cb, b);
 #pragma unroll
@@ -841,10 +847,49 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
 #pragma unroll
           for (int c = 0; c < 3; ++c) acc[k].v[s][c] = b.v[s][c] - acc[k].v[s][c];
       }
-      if (g.out_nt) store_spinor<S, true>(out, rhs[k], cb, acc[k]);
-      else store_spinor<S>(out, rhs[k], cb, acc[k]);
+      if constexpr (DOT != DOT_RES_ENC) {
+        if (g.out_nt) store_spinor<S, true>(out, rhs[k], cb, acc[k]);
+        else store_spinor<S>(out, rhs[k], cb, acc[k]);
+      }
     }
-    if constexpr (DOT != DOT_NONE) {
+    if constexpr (DOT == DOT_RES_ENC) {
+      using R2 = typename S2::real;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      if (valid) {
+        Spinor<R2> e, z, t;
+        double nn = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
+            e.v[s][c] = {static_cast<R2>(acc[k].v[s][c].re), static_cast<R2>(acc[k].v[s][c].im)};
+            z.v[s][c] = {R2(0), R2(0)};
+          }
+        store_spinor<S2>(enc.rh, rhs[k], cb, e);
+        store_spinor<S2>(enc.xh, rhs[k], cb, z);
+        // the dots see the stored (re-encoded) residual
+        load_spinor<S2>(enc.rh, rhs[k], cb, e);
+        load_spinor<S2>(enc.rt, rhs[k], cb, t);
+        R2 n2 = 0, re = 0, im = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            n2 += e.v[s][c].re * e.v[s][c].re + e.v[s][c].im * e.v[s][c].im;
+            const cx<R2> q = cmulc(t.v[s][c], e.v[s][c]);
+            re += q.re;
+            im += q.im;
+          }
+        d[0] = nn;
+        d[1] = n2;
+        d[2] = re;
+        d[3] = im;
+      }
+      const int nb = (g.slab ? 8 : 1) * g.site_blocks;
+      block_sum_store<4>(d, partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot);
+    }
+    if constexpr (DOT != DOT_NONE && DOT != DOT_RES_ENC) {
       const int nb = (g.slab ? 8 : 1) * g.site_blocks;
       double* part = partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot;
       if constexpr (DOT == DOT_YO) {
@@ -965,26 +1010,41 @@ static size_t lds_stage_bytes(const DslashGeom& g, int nr) {
 template <class S, bool DAGGER, bool XPAY, int NR, int RECON, bool LDS, int BASIS>
 static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
                        const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy,
-                       typename S::real a, int p, const int* sel, double* partials) {
+                       typename S::real a, int p, const int* sel, double* partials, EncView enc,
+                       wd_prec enc_prec) {
   if constexpr (BASIS == kBasisDR) {
-    dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+    dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
   } else {
     switch (dot) {
       case DOT_YO:
-        dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_YO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OX:
-        dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_OX, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OO:
-        dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_OO, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_RES:
         if constexpr (S::prec == WD_FP64 && XPAY && !DAGGER && !LDS)
-          dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+          dslash_kernel<S, DAGGER, XPAY, DOT_RES, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        break;
+      case DOT_RES_ENC:
+        if constexpr (S::prec == WD_FP64 && XPAY && !DAGGER && !LDS) {
+          switch (enc_prec) {
+            case WD_FP32:
+              dslash_kernel<S, DAGGER, XPAY, DOT_RES_ENC, NR, RECON, LDS, BASIS, SF32><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+              break;
+            case WD_HALF_I16:
+              dslash_kernel<S, DAGGER, XPAY, DOT_RES_ENC, NR, RECON, LDS, BASIS, SI16><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+              break;
+            default:
+              dslash_kernel<S, DAGGER, XPAY, DOT_RES_ENC, NR, RECON, LDS, BASIS, SF16><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+          }
+        }
         break;
       default:
-        dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials);
+        dslash_kernel<S, DAGGER, XPAY, DOT_NONE, NR, RECON, LDS, BASIS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
     }
   }
 }
@@ -1002,14 +1062,15 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   using R = typename S::real;
   const R ar = static_cast<R>(d.a);
   const int dot = d.xpay ? d.dot : DOT_NONE;
+  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt)};
   size_t lds = lds_for(c.wgs);
   if constexpr (LDS) lds = std::max(lds, lds_stage_bytes(g, NR));
   if (d.dagger) {
-    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
-    else launch_dot<S, true, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
+    if (d.xpay) launch_dot<S, true, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials, ev, d.enc_prec);
+    else launch_dot<S, true, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials, ev, d.enc_prec);
   } else {
-    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
-    else launch_dot<S, false, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials);
+    if (d.xpay) launch_dot<S, false, true, NR, RECON, LDS, BASIS>(dot, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials, ev, d.enc_prec);
+    else launch_dot<S, false, false, NR, RECON, LDS, BASIS>(DOT_NONE, grid, c.block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, d.rhs_map ? d.rhs_map : d.active, d.partials, ev, d.enc_prec);
   }
 }
 

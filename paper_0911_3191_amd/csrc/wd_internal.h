@@ -61,8 +61,11 @@ namespace wd {
 // ---- launchers (defined in the .hip files; all asynchronous on `s`) -------------
 constexpr int kMaxDotHost = 4;  // doubles per partial record
 // DOT_RES (FP64 only): out = y - (xpay + a D in), the residual of a reliable
-// update, with |out|^2 partials.
-enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4 };
+// update, with |out|^2 partials.  DOT_RES_ENC (FP64, UKQCD basis): the same
+// residual r is not stored in FP64 but re-encoded straight into the inner
+// solver's fields: enc_rh = enc(r), enc_xh = 0, partials |r|^2, |enc(r)|^2,
+// <enc_rt, enc(r)> (the last two on the stored values).
+enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4, DOT_RES_ENC = 5 };
 
 // Full argument set of one dslash launch.  out = D in, or, with xpay set,
 // out = *xpay + a * D in; with xpay and dot set, per-block FP64 partials of
@@ -86,6 +89,12 @@ struct DslashArgs {
   const int* rhs_map = nullptr;
   int n_map = 0;
   int basis = kBasisDR;  // spin basis of the fields (fused dots: UKQCD only)
+  // DOT_RES_ENC: the inner precision and its residual, zeroed solution and
+  // shadow residual fields
+  wd_prec enc_prec = WD_FP32;
+  const Field* enc_rh = nullptr;
+  const Field* enc_xh = nullptr;
+  const Field* enc_rt = nullptr;
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 
@@ -159,7 +168,8 @@ enum ScalarSlot {
 enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_COUNT = 4 };
 enum FinStage {
   FIN_B2_FIRST, FIN_B2_ADD, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
-  FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO
+  FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO,
+  FIN_TRUE_RHO  // FIN_TRUE on v[0], then FIN_RHO on v[1..3] where iteration goes on
 };
 
 hipError_t blas_bicg_p(const Geom& g, wd_prec pr, Field p, Field r, Field v, const double* sc,

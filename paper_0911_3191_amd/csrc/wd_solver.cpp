@@ -117,10 +117,9 @@ static hipError_t mhat_into(wd_solver* h, wd_prec prec, const Field& out, const 
   return dslash_into(h, prec, out, tmp_odd, 0, dagger, &in, -h->kappa * h->kappa, dot, y, mask);
 }
 
-static hipError_t fin(wd_solver* h, int stage, const int* mask) {
-  // the stages that follow a dslash with a fused dot read the dslash's partial records
-  const bool after_dslash =
-      stage == FIN_BICG_ALPHA || stage == FIN_BICG_OMEGA || stage == FIN_CG_ALPHA || stage == FIN_TRUE;
+// after_dslash: the partial records come from a dslash with a fused dot
+// (its record count per RHS), else from a BLAS-1 kernel.
+static hipError_t fin(wd_solver* h, int stage, const int* mask, bool after_dslash) {
   return solver_finalize(stage, h->nrhs, after_dslash ? h->nb_dslash : h->nb, h->partials, h->sc,
                          h->fl, h->active, h->rumask, mask, h->prm.delta, h->prm.tol, h->prm.restart,
                          h->s);
@@ -140,19 +139,19 @@ static hipError_t iteration_body(wd_solver* h) {
   if (h->kind == WD_SOLVER_BICGSTAB) {
     WD_TRY(blas_bicg_p(g, P, h->p, h->rh, h->v, h->sc, act, h->s));
     WD_TRY(mhat_into(h, P, h->v, h->p, h->to, 0, DOT_YO, &h->rt, act));  // v = M p, <r~, v>
-    WD_TRY(fin(h, FIN_BICG_ALPHA, act));
+    WD_TRY(fin(h, FIN_BICG_ALPHA, act, true));
     WD_TRY(blas_bicg_s(g, P, h->rh, h->v, h->sc, act, h->s));           // s = r - alpha v
     WD_TRY(mhat_into(h, P, h->t, h->rh, h->to, 0, DOT_OX, nullptr, act));  // t = M s, <t,s>, |t|^2
-    WD_TRY(fin(h, FIN_BICG_OMEGA, act));
+    WD_TRY(fin(h, FIN_BICG_OMEGA, act, true));
     WD_TRY(blas_bicg_xr(g, P, h->xh, h->rh, h->p, h->t, h->rt, h->sc, act, h->partials, h->s));
-    WD_TRY(fin(h, FIN_BICG_ITER, act));
+    WD_TRY(fin(h, FIN_BICG_ITER, act, false));
   } else {
     // w = M p (|w|^2), q = M^dag w, x^ += alpha p, r^ -= alpha q
     WD_TRY(mhat_into(h, P, h->t, h->p, h->to, 0, DOT_OO, nullptr, act));
-    WD_TRY(fin(h, FIN_CG_ALPHA, act));
+    WD_TRY(fin(h, FIN_CG_ALPHA, act, true));
     WD_TRY(mhat_into(h, P, h->v, h->t, h->to, 1, DOT_NONE, nullptr, act));
     WD_TRY(blas_cg_xr(g, P, h->xh, h->rh, h->p, h->v, h->sc, act, h->partials, h->s));
-    WD_TRY(fin(h, FIN_CG_ITER, act));
+    WD_TRY(fin(h, FIN_CG_ITER, act, false));
   }
   return hipSuccess;
 }
@@ -161,8 +160,11 @@ static hipError_t iteration_body(wd_solver* h) {
 // convergence test.  The subtraction from b_hat and |r|^2 are fused into the
 // second dslash.  With n_map > 0 the dslash launches cover only the n_map RHS
 // listed in h->rumap (the same set as mask), packed into as few RHS groups as
-// they fill, rather than the whole batch with most of it masked off.
-static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0) {
+// they fill, rather than the whole batch with most of it masked off.  With
+// reencode (BiCGstab with reliable updates) the second dslash does not store
+// r in FP64 but re-encodes it into r^ itself, zeroes x^ and returns
+// <r~, r^> and |r^|^2 beside |r|^2: the whole re-seed of the inner solver.
+static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0, bool reencode = false) {
   DslashArgs d;
   d.out = h->to64;
   d.in = h->x;
@@ -180,35 +182,39 @@ static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0) {
   d.out_parity = 0;
   d.xpay = &h->x;
   d.a = -h->kappa * h->kappa;
-  d.dot = DOT_RES;
+  d.dot = reencode ? DOT_RES_ENC : DOT_RES;
   d.y = &h->bhat;
+  d.enc_prec = h->prm.inner;
+  d.enc_rh = &h->rh;
+  d.enc_xh = &h->xh;
+  d.enc_rt = &h->rt;
   WD_TRY(launch_dslash_ex(h->g, WD_FP64, d, h->s));
-  WD_TRY(fin(h, FIN_TRUE, mask));
+  WD_TRY(fin(h, reencode ? FIN_TRUE_RHO : FIN_TRUE, mask, true));
   return hipSuccess;
 }
 
-// Re-seed the inner residual from the FP64 one (and zero x^) for the RHS in rumask.
-// Defect correction restarts BiCGstab there: new shadow residual, p = v = 0
-// and the scalars of a first iteration.  (CG restarts through beta = 0 at
-// FIN_CG_RHO, so that the p update after the step sets p = r^.)
-static hipError_t reseed(wd_solver* h, bool first) {
+// Re-seed the inner residual from the FP64 one r64 (and zero x^) for the RHS
+// in rumask.  Defect correction restarts BiCGstab there: new shadow residual,
+// p = v = 0 and the scalars of a first iteration.  (CG restarts through
+// beta = 0 at FIN_CG_RHO, so that the p update after the step sets p = r^.)
+static hipError_t reseed(wd_solver* h, bool first, const Field& r64) {
   const Geom& g = h->geom;
   const wd_prec P = h->prm.inner;
   if (h->kind == WD_SOLVER_BICGSTAB) {
     const bool fresh = first || h->prm.restart;
-    if (fresh) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, h->r, h->rumask, h->s));  // r~ = r
+    if (fresh) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, r64, h->rumask, h->s));  // r~ = r
     if (!first && h->prm.restart) {
       WD_TRY(blas_zero(g, P, h->p, h->rumask, h->s));
       WD_TRY(blas_zero(g, P, h->v, h->rumask, h->s));
     }
-    WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->r, &h->rt, h->rumask, h->partials, h->s));
-    WD_TRY(fin(h, fresh ? FIN_BICG_INIT : FIN_RHO, h->rumask));
+    WD_TRY(blas_reencode(g, P, h->rh, h->xh, r64, &h->rt, h->rumask, h->partials, h->s));
+    WD_TRY(fin(h, fresh ? FIN_BICG_INIT : FIN_RHO, h->rumask, false));
   } else {
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
     // normal-equation residual M_hat^dag r in FP64
-    WD_TRY(mhat_into(h, WD_FP64, h->rn, h->r, h->to64, 1, DOT_NONE, nullptr, h->rumask));
+    WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask));
     WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->rn, nullptr, h->rumask, h->partials, h->s));
-    WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask));
+    WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask, false));
     if (first) WD_TRY(blas_convert(g, P, h->p, P, h->rh, h->rumask, h->s));  // p = r^
   }
   return hipSuccess;
@@ -224,8 +230,10 @@ static hipError_t reliable_update(wd_solver* h) {
   else
     n = 0;  // every RHS (or, defensively, none listed): the mask alone
   WD_TRY(blas_accum(h->geom, h->prm.inner, h->x, h->xh, h->rumask, h->s));  // x += x^
-  WD_TRY(true_residual(h, h->rumask, n));                                    // r = b - M x
-  WD_TRY(reseed(h, false));                                                  // r^ = r, x^ = 0
+  if (h->kind == WD_SOLVER_BICGSTAB && !h->prm.restart && h->prm.inner != WD_FP64)
+    return true_residual(h, h->rumask, n, true);  // r = b - M x; r^ = r, x^ = 0 in the same pass
+  WD_TRY(true_residual(h, h->rumask, n));  // r = b - M x
+  WD_TRY(reseed(h, false, h->r));          // r^ = r, x^ = 0
   return hipSuccess;
 }
 
@@ -258,20 +266,22 @@ static hipError_t prepare(wd_solver* h) {
   WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK));
   WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK));
   WD_TRY(blas_norm2(g, WD_FP64, h->r, nullptr, h->partials, h->s));
-  WD_TRY(fin(h, FIN_B2_FIRST, nullptr));
+  WD_TRY(fin(h, FIN_B2_FIRST, nullptr, false));
   WD_TRY(blas_norm2(g, WD_FP64, h->to64, nullptr, h->partials, h->s));
-  WD_TRY(fin(h, FIN_B2_ADD, nullptr));
+  WD_TRY(fin(h, FIN_B2_ADD, nullptr, false));
   // solve for b / |b| (unit source per RHS); x is scaled back at reconstruction
   WD_TRY(blas_scale_bnorm(g, h->r, h->sc, 1, h->s));
   WD_TRY(blas_scale_bnorm(g, h->to64, h->sc, 1, h->s));
   // b_hat = b_e + kappa D_eo b_o
   WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_NONE, nullptr, nullptr));
   WD_TRY(blas_zero(g, WD_FP64, h->x, nullptr, h->s));
-  // r = b_hat - M_hat 0 via the same path as every reliable update
-  WD_TRY(true_residual(h, nullptr));
+  // x = 0, so r = b_hat - M_hat x is b_hat exactly: the convergence test and
+  // the first inner residual read b_hat (no dslash needed)
+  WD_TRY(blas_norm2(g, WD_FP64, h->bhat, nullptr, h->partials, h->s));
+  WD_TRY(fin(h, FIN_TRUE, nullptr, false));
   WD_TRY(blas_zero(g, h->prm.inner, h->p, nullptr, h->s));
   WD_TRY(blas_zero(g, h->prm.inner, h->v, nullptr, h->s));
-  WD_TRY(reseed(h, true));
+  WD_TRY(reseed(h, true, h->bhat));
   return hipSuccess;
 }
 
