@@ -183,6 +183,9 @@ def parse():
                     help="requests of the Poisson serving run (0: skip it)")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter scaling)")
+    ap.add_argument("--rhs-scan", action="store_true",
+                    help="also time the FP64 and inner-precision dslash against the number of RHS "
+                         "per launch (1, 2, 3, 4, 6, 12)")
     return ap.parse_args()
 
 
@@ -366,6 +369,31 @@ def main():
                        "gflops": round(1320 * Vh / t / 1e9, 1)}
         del fi, fo
     log(f"dslash table {table}")
+    rhs_scan = None
+    if args.rhs_scan:
+        # cost of each added right-hand side in one launch (tuned shapes)
+        rhs_scan = {}
+        for prec in ("fp64", inner):
+            rows = {}
+            for n in (1, 2, 3, 4, 6, NRHS):
+                fi = wd.new_field(lat, prec, n)
+                fo = wd.new_field(lat, prec, n)
+                with torch.cuda.stream(stream):
+                    wd.wd_spinor_encode_basis(lat, prec, n, UK, fi, gsrc[0:n], stream)
+                    for _ in range(3):
+                        wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(args.dslash_reps):
+                        wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+                    e1.record(stream)
+                e1.synchronize()
+                t = e0.elapsed_time(e1) / args.dslash_reps * 1e-3
+                rows[n] = {"us": round(t * 1e6, 1),
+                           "alg_GB/s": round(dslash_bytes(prec, n) * Vh / t / 1e9, 1)}
+                del fi, fo
+            rhs_scan[prec] = rows
+        log(f"rhs scan {rhs_scan}")
     del gsrc
     torch.cuda.empty_cache()
 
@@ -475,6 +503,7 @@ def main():
                                                     if fp64 else None),
                              "defect_correction": dc},
         "dslash_single_rhs": table,
+        "dslash_rhs_scan": rhs_scan,
         "copy_GBps": round(copy_gbs, 1),
         "other_configs": others,
         "serve": serve,
