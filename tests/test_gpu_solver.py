@@ -106,6 +106,26 @@ def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone():
             assert info1["reliable_updates"] == infos[k]["reliable_updates"]
 
 
+@pytest.mark.parametrize("shape", ["3,0,2,1,0,0,0", "4,1,2,0,0,0,0", "1,1,2,0,0,0,1"])
+def test_batch_under_any_launch_shape_equals_each_rhs_alone(shape, monkeypatch):
+    """Launches with a fused dot product keep one sub-slab, so their partial
+    records cover the same sites whatever else the shape says (RHS per thread,
+    group order, link cache policy, LDS staging): a batch solved under a forced
+    shape matches each RHS solved alone, bit for bit."""
+    dims, kappa = (8, 4, 8, 6), 0.124
+    U = wdinputs.gauge_random(dims, 0.4, 15)
+    s = Setup(dims, U)
+    bs = wdinputs.spinor_gaussian(dims, 16, nrhs=5)
+    monkeypatch.setenv("WD_DSLASH_SHAPE", shape)
+    st, xb, infos = run(s, "bicgstab", bs, kappa, tol=1e-12, inner="f16", delta=0.1, nrhs=5)
+    assert st == wd.WD_OK
+    monkeypatch.delenv("WD_DSLASH_SHAPE")
+    for k in range(5):
+        st1, x1, info1 = run(s, "bicgstab", bs[k], kappa, tol=1e-12, inner="f16", delta=0.1)
+        assert np.array_equal(x1, xb[k]), f"{shape} rhs {k}"
+        assert info1["iters"] == infos[k]["iters"]
+
+
 @pytest.mark.parametrize("solver", ["bicgstab", "cg"])
 def test_graph_replay_matches_direct_launches(solver):
     dims, kappa = (8, 8, 8, 8), 0.12
