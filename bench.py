@@ -20,6 +20,13 @@ Reported:
                    (FETCH_SIZE + WRITE_SIZE from the committed counter summary,
                    when it was taken on the current kernel source)
   time_to_solution mixed 12-RHS batch vs the plain FP64 single-RHS BiCGstab
+  dslash_single_rhs the single-RHS dslash in every storage precision
+  stream_GBps      what plain torch streaming kernels reach on the same device
+                   (read only, write only, copy, two reads + one write): the
+                   practical ceiling beside the nominal 8 TB/s
+  dslash_rhs_scan  (--rhs-scan) dslash time against the RHS count per launch
+  other_configs    time to solution on the smaller lattices, mixed vs FP64
+  serve            the Poisson serving run (latency percentiles, solves/s)
   cpu_baseline     the FP64 oracle's own BiCGstab on source 0, stopped after one
                    and after two iterations: the difference is one iteration
 """
@@ -411,6 +418,25 @@ def main():
     c1.synchronize()
     copy_gbs = 2 * ncopy * 8 / (c0.elapsed_time(c1) / 5 * 1e-3) / 1e9
     log(f"copy: {ncopy * 8 / 1e9:.2f} GB read + written at {copy_gbs:.0f} GB/s")
+
+    # practical streaming rates of plain torch kernels on the same buffers (context for
+    # the 8 TB/s peak): read only, write only, and two reads + one write
+    def stream_rate(fn, nbytes):
+        with torch.cuda.stream(stream):
+            fn()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            for _ in range(5):
+                fn()
+            s1.record(stream)
+        s1.synchronize()
+        return round(nbytes / (s0.elapsed_time(s1) / 5 * 1e-3) / 1e9, 1)
+    nb = ncopy * 8
+    stream_gbs = {"read": stream_rate(lambda: src.sum(), nb),
+                  "write": stream_rate(lambda: dst.fill_(1.0), nb),
+                  "copy": round(copy_gbs, 1),
+                  "read2_write1": stream_rate(lambda: dst.add_(src), 3 * nb)}
+    log(f"streaming rates {stream_gbs}")
     del src, dst
 
     # ---- the smaller configurations: time to solution, mixed against FP64 ----
@@ -505,6 +531,7 @@ def main():
         "dslash_single_rhs": table,
         "dslash_rhs_scan": rhs_scan,
         "copy_GBps": round(copy_gbs, 1),
+        "stream_GBps": stream_gbs,
         "other_configs": others,
         "serve": serve,
         "cpu_baseline": cpu,
