@@ -56,6 +56,22 @@ NRHS = 12
 # spinor 24 reals (+ a 4-byte norm for 16-bit), link 12 reals.
 SPINOR_B = {"fp64": 192, "fp32": 96, "i16": 52, "f16": 52}
 LINK_B = {"fp64": 96, "fp32": 48, "i16": 24, "f16": 24}
+# The paper's own per-site count for one RHS (Section 4.3, no reuse of
+# neighbours): 8 x (24 spinor + 12 link) reals loaded and 24 stored, plus, in
+# 16-bit storage, 9 norms.
+PAPER_MODEL_B = {"fp64": 8 * 36 * 8 + 24 * 8, "fp32": 8 * 36 * 4 + 24 * 4,
+                 "i16": 8 * 36 * 2 + 24 * 2 + 9 * 4, "f16": 8 * 36 * 2 + 24 * 2 + 9 * 4}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def dslash_bytes(prec: str, nrhs: int, xpay: int = 0) -> int:
@@ -373,7 +389,8 @@ def main():
         t = e0.elapsed_time(e1) / args.dslash_reps * 1e-3
         gbs = dslash_bytes(prec, 1) * Vh / t / 1e9
         table[prec] = {"us": round(t * 1e6, 1), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                       "gflops": round(1320 * Vh / t / 1e9, 1)}
+                       "gflops": round(1320 * Vh / t / 1e9, 1),
+                       "paper_model_GB/s": round(PAPER_MODEL_B[prec] * Vh / t / 1e9, 1)}
         del fi, fo
     log(f"dslash table {table}")
     rhs_scan = None
@@ -484,6 +501,7 @@ def main():
         # the same step on the oracle: every iteration of every RHS (reliable updates not counted)
         cpu_value = bicgstab_iter_bytes(inner, NRHS) * Vh / (t_iter * NRHS) / 1e9
         cpu = {"value": round(cpu_value, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                "sample": (f"FP64 oracle BiCGstab on source 0 of {args.dims}, stopped after 1 and after 2 "
                           f"iterations ({times[1]:.1f} s, {times[2]:.1f} s); one iteration = {t_iter:.2f} s; "
                           f"value = the step's algorithmic bytes per batch iteration / ({NRHS} x that time)")}
@@ -514,7 +532,8 @@ def main():
                      "kernel": f"dslash_kernel<{inner}> {NRHS}-RHS, UKQCD basis",
                      "bytes_per_launch": dbytes, "us_per_launch": round(t_dslash * 1e6, 1),
                      "flops_per_launch": dflops, "alu_achieved_TFLOPs": round(tflops, 2),
-                     "alu_frac": round(tflops / ALU_PEAK_TFLOPS, 4)},
+                     "alu_frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+                     "paper_model_GBps": round(NRHS * PAPER_MODEL_B[inner] * Vh / t_dslash / 1e9, 1)},
         "time_to_solution": {"mixed_batch_s": round(ms_per_step * 1e-3, 3),
                              "mixed_per_rhs_s": round(per_rhs_mixed, 4),
                              "fp64_single_rhs_s": round(fp64["seconds"], 3) if fp64 else None,
