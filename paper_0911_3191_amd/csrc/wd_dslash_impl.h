@@ -122,12 +122,14 @@ struct SpinorBuf {
   uint32_t chunk_bytes;           // stride * 16
 };
 
+// on = false gives an empty buffer (every load from it reads zero and moves
+// no data), so a thread's RHS slots need no branches.
 template <class S>
-__device__ __forceinline__ SpinorBuf<S> spinor_buf(const FieldView& f, int r) {
+__device__ __forceinline__ SpinorBuf<S> spinor_buf(const FieldView& f, int r, bool on = true) {
   SpinorBuf<S> b;
   b.chunk_bytes = (uint32_t)(f.stride * 16);
-  b.chunks = make_rsrc(chunk_base<S>(f, r, 0), b.chunk_bytes * S::NCH);
-  if constexpr (kHalf<S>) b.norms = make_rsrc(norm_base(f, r), (uint32_t)(f.stride * 4));
+  b.chunks = make_rsrc(chunk_base<S>(f, r, 0), on ? b.chunk_bytes * S::NCH : 0u);
+  if constexpr (kHalf<S>) b.norms = make_rsrc(norm_base(f, r), on ? (uint32_t)(f.stride * 4) : 0u);
   else b.norms = b.chunks;
   return b;
 }
@@ -356,18 +358,14 @@ __device__ __forceinline__ void unit_link(Link<R>& L) {
     for (int b = 0; b < 3; ++b) L.u[a][b] = {a == b ? R(1) : R(0), R(0)};
 }
 
-// Link of (par, mu) at site i in the handle's format, with the launch's cache
-// policy for links.
+// Link of (par, mu) at site i in the handle's format.  (A streaming cache
+// hint on link loads gained 3% for one RHS, but choosing it at run time puts a
+// branch in every hop, which splits the scheduling regions and costs more.)
 template <class S, int RECON>
 __device__ __forceinline__ void gather_link(const DslashGeom& g, const char* links, int par, int mu, int i,
                                             Link<typename S::real>& L) {
-  if constexpr (RECON == 8) {
-    if (g.link_nt) gather_link8<S, kStream>(links, g.stride, par, mu, i, L);
-    else gather_link8<S, 0>(links, g.stride, par, mu, i, L);
-  } else {
-    if (g.link_nt) gather_link_aux<S, kStream>(links, g.stride, par, mu, i, L);
-    else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
-  }
+  if constexpr (RECON == 8) gather_link8<S, 0>(links, g.stride, par, mu, i, L);
+  else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
 }
 
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -586,6 +584,25 @@ __device__ __forceinline__ void lds_gather16(const LdsCtx& c, int k, int sl, Raw
   }
 }
 
+// Splits the hops into one scheduling region per direction: every
+// accumulator is pinned (empty asm, value in a register, memory clobber), so a
+// direction's arithmetic completes before the next direction's loads are
+// issued.  Without it the compiler either drains the loads of each RHS slot
+// before issuing the next (few loads in flight per wave) or, in straight-line
+// code, hoists every load of all eight hops and runs out of registers.
+template <typename R, int NR>
+__device__ __forceinline__ void hop_fence(Spinor<R> (&acc)[NR]) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        asm volatile("" : "+v"(acc[k].v[s][c].re) : : "memory");
+        asm volatile("" : "+v"(acc[k].v[s][c].im) : : "memory");
+      }
+}
+
 // Both hops of direction MU for the NR right-hand sides of this thread.
 template <class S, int MU, bool DAGGER, int NR, int RECON, bool LDS, int BASIS>
 __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
@@ -638,8 +655,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
     if (unit_f) unit_link(U);
     else gather_link<S, RECON>(g, links, p, MU, cb, U);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      if (!on[k]) continue;
+    for (int k = 0; k < NR; ++k) {  // an empty slot reads zeros (see spinor_buf)
       if constexpr (MU == 3 && BASIS == kBasisUK) {
         // 1 - gamma_t keeps the lower spins, its adjoint 1 + gamma_t the upper ones
         constexpr int BASE = DAGGER ? 0 : 2;
@@ -667,6 +683,8 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
       }
     }
   }
+  // FP64 spinors are large enough that one hop's loads fill the registers
+  if constexpr (S::prec == WD_FP64) hop_fence<R, NR>(acc);
   // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
   {
     Link<R> U;
@@ -674,7 +692,6 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
     else gather_link<S, RECON>(g, links, 1 - p, MU, nb, U);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      if (!on[k]) continue;
       if constexpr (MU == 3 && BASIS == kBasisUK) {
         // 1 + gamma_t keeps the upper spins, its adjoint 1 - gamma_t the lower ones
         constexpr int BASE = DAGGER ? 2 : 0;
@@ -821,11 +838,15 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     const float one = pin_f32(1.0f);  // see proj16
     SpinorBuf<S> ib[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0);
+    for (int k = 0; k < NR; ++k) ib[k] = spinor_buf<S>(in, on[k] ? rhs[k] : 0, on[k]);
     hop_pair<S, 0, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_fence<R, NR>(acc);
     hop_pair<S, 1, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_fence<R, NR>(acc);
     hop_pair<S, 2, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_fence<R, NR>(acc);
     hop_pair<S, 3, DAGGER, NR, RECON, LDS, BASIS>(acc, g, links, ib, on, p, cb, xh, row, X, one, lc);
+    hop_fence<R, NR>(acc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
@@ -1074,11 +1095,10 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   }
 }
 
-// Threads carry at least two RHS slots: with one, the compiler keeps every
-// gather of a site in flight and runs out of registers (a single RHS leaves
-// the second slot empty).  8-real links are built for two slots only (their
-// rebuild is long; wider shapes gain little when links are a small part of
-// the bytes).
+// Threads carry 1 to 4 RHS slots (a slot past the last RHS reads zeros and
+// its arithmetic is wasted, so one RHS runs in a one-slot thread).  8-real
+// links are built for one and two slots only (their rebuild is long; wider
+// shapes gain little when links are a small part of the bytes).
 // The LDS-staged variant exists for the 16-bit formats with 12-real links and
 // 2 or 3 slots, on the slab mapping, when its staging fits 62 KiB.
 static bool lds_usable(const wd_gauge* gg, wd_prec prec, const LaunchCfg& c) {
@@ -1094,7 +1114,8 @@ static bool lds_usable(const wd_gauge* gg, wd_prec prec, const LaunchCfg& c) {
 template <class S, int BASIS>
 static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
   if (gg->recon == 8) {
-    launch_nr<S, 2, 8, false, BASIS>(gg, d, c, s);
+    if (c.nr == 1) launch_nr<S, 1, 8, false, BASIS>(gg, d, c, s);
+    else launch_nr<S, 2, 8, false, BASIS>(gg, d, c, s);
     return;
   }
   if constexpr (kHalf<S>) {
@@ -1105,6 +1126,7 @@ static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg&
     }
   }
   switch (c.nr) {
+    case 1: launch_nr<S, 1, 12, false, BASIS>(gg, d, c, s); break;
     case 3: launch_nr<S, 3, 12, false, BASIS>(gg, d, c, s); break;
     case 4: launch_nr<S, 4, 12, false, BASIS>(gg, d, c, s); break;
     default: launch_nr<S, 2, 12, false, BASIS>(gg, d, c, s); break;

@@ -1,7 +1,8 @@
 // Autotuner for the dslash launch shape: right-hand sides per thread (nr),
 // y-sub-slabs of an XCD's sweep (nsub, shortens the reuse distance of the
-// t-neighbours), the cache policy of the link loads (link_nt) and, for the
-// 16-bit formats, LDS staging of the x/y neighbours (lds).
+// t-neighbours) and, for the 16-bit formats, LDS staging of the x/y
+// neighbours (lds).  (link_nt, a cache hint for link loads, is still parsed
+// but the kernels no longer use it and it is not searched.)
 //
 // The first eager launch for a (lattice, precision, nrhs) times each
 // candidate with HIP events on the caller's stream, using the plain
@@ -42,7 +43,7 @@ Key key_of(const wd_gauge* g, wd_prec prec, int nrhs, int basis) {
              (g->recon == 8 ? 1 : 0) | (g->tgauge ? 2 : 0) | (basis == kBasisUK ? 4 : 0)};
 }
 
-LaunchCfg default_cfg(wd_prec, int) { return LaunchCfg{2, 256}; }
+LaunchCfg default_cfg(wd_prec, int nrhs) { return LaunchCfg{nrhs == 1 ? 1 : 2, 256}; }
 
 const char* cache_path() {
   const char* p = std::getenv("WD_TUNE_CACHE");
@@ -122,16 +123,18 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
   plain.y = nullptr;
   LaunchCfg best = default_cfg(prec, d.out.nrhs);
   float best_ms = -1.0f;
-  // Kernels carry 2..4 RHS slots per thread (a single RHS runs in a
-  // two-slot thread with the second slot empty).
+  // Kernels carry 1..4 RHS slots per thread (one RHS also tries a two-slot
+  // thread: its empty slot costs arithmetic but no memory traffic, and in FP64
+  // the two-slot kernel has measured faster).
   const bool slab = g->geom.L[2] % 8 == 0;
-  for (int nr = 2; nr <= 4; ++nr) {
+  for (int nr = 1; nr <= 4; ++nr) {
     if (nr > std::max(d.out.nrhs, 2)) break;
     if (g->recon == 8 && nr > 2) break;  // 8-real kernels exist for two slots
     for (int nsub = 1; nsub <= (slab ? 4 : 1); nsub *= 2) {
       if (g->geom.L[1] % nsub) continue;
       for (int v = 0; v < 4; ++v) {
         const int nt = v & 1, lds = v >> 1;
+        if (nt) continue;  // the link cache hint is not used by the kernels
         if (lds && !(is_half(prec) && nr <= 3 && g->recon == 12 && slab)) continue;
         const int gslow = 0;
         LaunchCfg c{nr, 256, gslow, nsub, nt};
