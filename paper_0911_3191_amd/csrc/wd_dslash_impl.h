@@ -358,14 +358,15 @@ __device__ __forceinline__ void unit_link(Link<R>& L) {
     for (int b = 0; b < 3; ++b) L.u[a][b] = {a == b ? R(1) : R(0), R(0)};
 }
 
-// Link of (par, mu) at site i in the handle's format.  (A streaming cache
-// hint on link loads gained 3% for one RHS, but choosing it at run time puts a
-// branch in every hop, which splits the scheduling regions and costs more.)
-template <class S, int RECON>
+// Link of (par, mu) at site i in the handle's format.  AUX is the cache
+// policy, fixed per kernel (a run-time choice would put a branch in every
+// hop, which splits the scheduling regions): one-slot kernels mark links
+// streaming, since a single RHS group reads each link exactly once.
+template <class S, int RECON, int AUX>
 __device__ __forceinline__ void gather_link(const DslashGeom& g, const char* links, int par, int mu, int i,
                                             Link<typename S::real>& L) {
-  if constexpr (RECON == 8) gather_link8<S, 0>(links, g.stride, par, mu, i, L);
-  else gather_link_aux<S, 0>(links, g.stride, par, mu, i, L);
+  if constexpr (RECON == 8) gather_link8<S, AUX>(links, g.stride, par, mu, i, L);
+  else gather_link_aux<S, AUX>(links, g.stride, par, mu, i, L);
 }
 
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -653,7 +654,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
   {
     Link<R> U;
     if (unit_f) unit_link(U);
-    else gather_link<S, RECON>(g, links, p, MU, cb, U);
+    else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, p, MU, cb, U);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {  // an empty slot reads zeros (see spinor_buf)
       if constexpr (MU == 3 && BASIS == kBasisUK) {
@@ -689,7 +690,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
   {
     Link<R> U;
     if (unit_b) unit_link(U);
-    else gather_link<S, RECON>(g, links, 1 - p, MU, nb, U);
+    else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, 1 - p, MU, nb, U);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if constexpr (MU == 3 && BASIS == kBasisUK) {
