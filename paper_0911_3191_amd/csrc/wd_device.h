@@ -244,53 +244,4 @@ __device__ __forceinline__ const char* link_chunk(const char* base, int64_t stri
   return base + ((int64_t)((par * 4 + mu) * LinkChunks<S>::N + k) * stride) * LinkChunks<S>::BYTES;
 }
 
-// Load rows a and b of a link and rebuild c = (a x b)^* (Appendix A.1).
-template <class S>
-__device__ __forceinline__ void load_link(const char* base, int64_t stride, int par, int mu,
-                                          int64_t i, Link<typename S::real>& L) {
-  using R = typename S::real;
-  cx<R> e[6];
-  if constexpr (S::prec == WD_FP64) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      double2 c = reinterpret_cast<const double2*>(link_chunk<S>(base, stride, par, mu, k))[i];
-      e[k] = {c.x, c.y};
-    }
-  } else if constexpr (S::prec == WD_FP32) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float4 c = reinterpret_cast<const float4*>(link_chunk<S>(base, stride, par, mu, k))[i];
-      e[2 * k] = {c.x, c.y};
-      e[2 * k + 1] = {c.z, c.w};
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      uint2 c = reinterpret_cast<const uint2*>(link_chunk<S>(base, stride, par, mu, k))[i];
-      uint32_t w[2] = {c.x, c.y};
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        uint16_t lo = (uint16_t)(w[j] & 0xffffu), hi = (uint16_t)(w[j] >> 16);
-        if constexpr (S::prec == WD_HALF_I16) {
-          e[2 * k + j] = {(float)(int16_t)lo * (1.0f / 32767.0f), (float)(int16_t)hi * (1.0f / 32767.0f)};
-        } else {
-          e[2 * k + j] = {h16_to_f(lo), h16_to_f(hi)};
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    L.u[0][b] = e[b];
-    L.u[1][b] = e[3 + b];
-  }
-  // c_j = conj(a_{j+1} b_{j+2} - a_{j+2} b_{j+1})
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-    L.u[2][j] = conj(L.u[0][j1] * L.u[1][j2] - L.u[0][j2] * L.u[1][j1]);
-  }
-  (void)sizeof(R);
-}
-
 }  // namespace wd
