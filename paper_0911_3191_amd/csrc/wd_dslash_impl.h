@@ -223,15 +223,21 @@ __device__ __forceinline__ float fmar(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Third row c_j = conj(a_j1 b_j2 - a_j2 b_j1) of a 12-real link from its
-// rows a and b (Appendix A.1), each real part one chain of FMAs.
+// rows a and b (Appendix A.1).  In binary32 each real part is one chain of
+// four FMAs; in FP64 the two products are formed side by side and subtracted
+// (one instruction more, a shorter dependency chain: measured faster there).
 template <typename R>
 __device__ __forceinline__ void third_row(const cx<R> (&a)[3], const cx<R> (&b)[3], cx<R> (&c)[3]) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
     const cx<R> p = a[j1], q = b[j2], u = a[j2], v = b[j1];
-    c[j].re = fmar(p.re, q.re, fmar(-p.im, q.im, fmar(-u.re, v.re, u.im * v.im)));
-    c[j].im = fmar(u.re, v.im, fmar(u.im, v.re, fmar(-p.re, q.im, -(p.im * q.re))));
+    if constexpr (sizeof(R) == 8) {
+      c[j] = conj(p * q - u * v);
+    } else {
+      c[j].re = fmar(p.re, q.re, fmar(-p.im, q.im, fmar(-u.re, v.re, u.im * v.im)));
+      c[j].im = fmar(u.re, v.im, fmar(u.im, v.re, fmar(-p.re, q.im, -(p.im * q.re))));
+    }
   }
 }
 
@@ -496,13 +502,13 @@ __device__ __forceinline__ void gather_half(const SpinorBuf<S>& b, int i, cx<typ
 }
 
 // Spins BASE, BASE + 1 of a 16-bit neighbour: 6 packed words (upper: chunk 0
-// and the first half of chunk 1; lower: the second half of chunk 1 and chunk 2),
-// word 3 k + c = spin BASE + k, colour c.
+// and the first half of chunk 1; lower: the second half of chunk 1 and chunk 2).
 template <class S, int BASE>
-__device__ __forceinline__ void gather_half16_raw(const SpinorBuf<S>& b, int i, uint32_t (&w)[6], float& scale) {
+__device__ __forceinline__ void gather_half16(const SpinorBuf<S>& b, int i, cx<float> (&h)[2][3], float& scale) {
   const uint32_t vo = (uint32_t)i * 16u;
   const float nm = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.norms, (uint32_t)i * 4u, 0, 0));
   scale = (S::prec == WD_HALF_I16) ? nm * (1.0f / 32767.0f) : nm;
+  uint32_t w[6];
   if constexpr (BASE == 0) {
     const uint4 c0 = bload16(b.chunks, vo, 0);
     const uint2 c1 = bload8(b.chunks, vo, b.chunk_bytes);
@@ -512,111 +518,10 @@ __device__ __forceinline__ void gather_half16_raw(const SpinorBuf<S>& b, int i, 
     const uint4 c2 = bload16(b.chunks, vo, 2 * b.chunk_bytes);
     w[0] = c1.x; w[1] = c1.y; w[2] = c2.x; w[3] = c2.y; w[4] = c2.z; w[5] = c2.w;
   }
-}
-
-// The same spins decoded to binary32 (in units of the site norm).
-template <class S, int BASE>
-__device__ __forceinline__ void gather_half16(const SpinorBuf<S>& b, int i, cx<float> (&h)[2][3], float& scale) {
-  uint32_t w[6];
-  gather_half16_raw<S, BASE>(b, i, w, scale);
 #pragma unroll
   for (int n = 0; n < 6; ++n) {
     if constexpr (S::prec == WD_HALF_I16) h[n / 3][n % 3] = {(float)(int16_t)(w[n] & 0xffffu), (float)(int16_t)(w[n] >> 16)};
     else h[n / 3][n % 3] = {half_lo(w[n]), half_hi(w[n])};
-  }
-}
-
-// ---- binary16 temporal hop in the UKQCD basis -------------------------------------
-// There the half spinor of a temporal hop needs no projection arithmetic, so it
-// is the stored binary16 words themselves, and rows a, b of a binary16 link are
-// stored words too.  Their complex products are formed with v_dot2_f32_f16
-// (two binary16 products, exact in binary32, summed in binary32), one
-// instruction for the real and one for the imaginary part, on link words
-// rearranged once per hop for all RHS slots; products with the rebuilt third
-// row (binary32) stay FMAs.  Word layout: re in the low half, im in the high.
-// (12-real links only: 8-real links store no row as such.)
-typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
-  return __builtin_amdgcn_fdot2(__builtin_bit_cast(h16x2, a), __builtin_bit_cast(h16x2, b), c, false);
-}
-__device__ __forceinline__ uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }
-
-// Stored link rows as dot2 operands: for element n = 3 row + col, dot2(pr[n], h)
-// and dot2(pi[n], h) are the real and imaginary parts of U_n h (forward hop)
-// or of conj(U_n) h (backward hop, which multiplies by U^dagger).
-struct TLink16 {
-  uint32_t pr[6], pi[6];
-  cx<float> c[3];  // rebuilt third row
-};
-
-template <bool DAG_LINK, int AUX>
-__device__ __forceinline__ void gather_tlink16(const char* links, int64_t stride, int par, int i, bool unit,
-                                               TLink16& T) {
-  uint32_t w[6];
-  if (unit) {
-#pragma unroll
-    for (int n = 0; n < 6; ++n) w[n] = (n == 0 || n == 4) ? 0x3c00u : 0u;  // binary16 1.0 on the diagonal
-  } else {
-    const uint32_t cbytes = (uint32_t)(stride * 8);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(link_chunk<SF16>(links, stride, par, 3, 0), cbytes * 3);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint2 c = bload8<AUX>(rs, (uint32_t)i * 8u, k * cbytes);
-      w[2 * k] = c.x;
-      w[2 * k + 1] = c.y;
-    }
-  }
-  cx<float> a[3], b[3];
-#pragma unroll
-  for (int n = 0; n < 3; ++n) {
-    a[n] = {half_lo(w[n]), half_hi(w[n])};
-    b[n] = {half_lo(w[3 + n]), half_hi(w[3 + n])};
-  }
-  third_row(a, b, T.c);
-#pragma unroll
-  for (int n = 0; n < 6; ++n) {
-    if constexpr (!DAG_LINK) {
-      T.pr[n] = w[n] ^ 0x80000000u;  // (re, -im)
-      T.pi[n] = swap16(w[n]);        // (im, re)
-    } else {
-      T.pr[n] = w[n];                          // (re, im)
-      T.pi[n] = swap16(w[n]) ^ 0x00008000u;    // (-im, re)
-    }
-  }
-}
-
-// acc[BASE + k] += scale * W h_k for the two spins the projector keeps, W = U
-// (forward) or U^dagger (backward); h = 6 binary16 words (see gather_half16_raw).
-template <bool DAG_LINK, int BASE>
-__device__ __forceinline__ void mul_acc_half_h16(Spinor<float>& acc, const uint32_t (&h)[6], const TLink16& U,
-                                                 float scale) {
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const uint32_t h0 = h[3 * k], h1 = h[3 * k + 1], h2 = h[3 * k + 2];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float re, im;
-      if constexpr (!DAG_LINK) {
-        if (a < 2) {
-          re = dot2(U.pr[3 * a + 2], h2, dot2(U.pr[3 * a + 1], h1, dot2(U.pr[3 * a], h0, 0.0f)));
-          im = dot2(U.pi[3 * a + 2], h2, dot2(U.pi[3 * a + 1], h1, dot2(U.pi[3 * a], h0, 0.0f)));
-        } else {
-          cx<float> w = {0.0f, 0.0f};
-          w = cmac(w, U.c[0], cx<float>{half_lo(h0), half_hi(h0)});
-          w = cmac(w, U.c[1], cx<float>{half_lo(h1), half_hi(h1)});
-          w = cmac(w, U.c[2], cx<float>{half_lo(h2), half_hi(h2)});
-          re = w.re;
-          im = w.im;
-        }
-      } else {
-        // conj(U_2a) h_2, then the two stored rows
-        const cx<float> t = cmacc(cx<float>{0.0f, 0.0f}, U.c[a], cx<float>{half_lo(h2), half_hi(h2)});
-        re = dot2(U.pr[3 + a], h1, dot2(U.pr[a], h0, t.re));
-        im = dot2(U.pi[3 + a], h1, dot2(U.pi[a], h0, t.im));
-      }
-      acc.v[BASE + k][a].re = fmar(scale, re, acc.v[BASE + k][a].re);
-      acc.v[BASE + k][a].im = fmar(scale, im, acc.v[BASE + k][a].im);
-    }
   }
 }
 
@@ -762,19 +667,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
     unit_b = g.tgauge && X[3] != 0;
   }
   // forward: (1 - gamma_mu) U_x^mu psi(x + mu); adjoint: (1 + gamma_mu)
-  if constexpr (MU == 3 && BASIS == kBasisUK && S::prec == WD_HALF_F16 && RECON == 12) {
-    constexpr int BASE = DAGGER ? 0 : 2;  // spins kept by 1 - gamma_t (adjoint: 1 + gamma_t)
-    TLink16 T;
-    gather_tlink16<false, (NR == 1 ? kStream : 0)>(links, g.stride, p, cb, unit_f, T);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      uint32_t h[6];
-      float s16;
-      gather_half16_raw<S, BASE>(in[k], nf, h, s16);
-      const float sc = 2.0f * s16;
-      mul_acc_half_h16<false, BASE>(acc[k], h, T, flip_f ? -sc : sc);
-    }
-  } else {
+  {
     Link<R> U;
     if (unit_f) unit_link(U);
     else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, p, MU, cb, U);
@@ -810,19 +703,7 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
   // FP64 spinors are large enough that one hop's loads fill the registers
   if constexpr (S::prec == WD_FP64) hop_fence<R, NR>(acc);
   // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
-  if constexpr (MU == 3 && BASIS == kBasisUK && S::prec == WD_HALF_F16 && RECON == 12) {
-    constexpr int BASE = DAGGER ? 2 : 0;  // spins kept by 1 + gamma_t (adjoint: 1 - gamma_t)
-    TLink16 T;
-    gather_tlink16<true, (NR == 1 ? kStream : 0)>(links, g.stride, 1 - p, nb, unit_b, T);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      uint32_t h[6];
-      float s16;
-      gather_half16_raw<S, BASE>(in[k], nb, h, s16);
-      const float sc = 2.0f * s16;
-      mul_acc_half_h16<true, BASE>(acc[k], h, T, flip_b ? -sc : sc);
-    }
-  } else {
+  {
     Link<R> U;
     if (unit_b) unit_link(U);
     else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, 1 - p, MU, nb, U);
