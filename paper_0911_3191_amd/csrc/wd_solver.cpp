@@ -90,9 +90,11 @@ struct wd_solver {
 
 namespace wd {
 
+// With n_map > 0 the launch covers only the n_map RHS listed in h->rumap (the
+// same set as mask), packed into as few RHS groups as they fill.
 static hipError_t dslash_into(wd_solver* h, wd_prec prec, const Field& out, const Field& in,
                               int parity, int dagger, const Field* xpay, double a, int dot,
-                              const Field* y, const int* mask) {
+                              const Field* y, const int* mask, int n_map = 0) {
   DslashArgs d;
   d.out = out;
   d.in = in;
@@ -105,16 +107,20 @@ static hipError_t dslash_into(wd_solver* h, wd_prec prec, const Field& out, cons
   d.partials = h->partials;
   d.active = mask;
   d.basis = kBasisUK;
+  if (n_map > 0) {
+    d.rhs_map = h->rumap;
+    d.n_map = n_map;
+  }
   return launch_dslash_ex(h->g, prec, d, h->s);
 }
 
 // out_e = in_e - kappa^2 D_eo D_oe in_e (dagger: the adjoint), optional fused dot.
 static hipError_t mhat_into(wd_solver* h, wd_prec prec, const Field& out, const Field& in,
                             const Field& tmp_odd, int dagger, int dot, const Field* y,
-                            const int* mask) {
-  hipError_t e = dslash_into(h, prec, tmp_odd, in, 1, dagger, nullptr, 0.0, DOT_NONE, nullptr, mask);
+                            const int* mask, int n_map = 0) {
+  hipError_t e = dslash_into(h, prec, tmp_odd, in, 1, dagger, nullptr, 0.0, DOT_NONE, nullptr, mask, n_map);
   if (e != hipSuccess) return e;
-  return dslash_into(h, prec, out, tmp_odd, 0, dagger, &in, -h->kappa * h->kappa, dot, y, mask);
+  return dslash_into(h, prec, out, tmp_odd, 0, dagger, &in, -h->kappa * h->kappa, dot, y, mask, n_map);
 }
 
 // after_dslash: the partial records come from a dslash with a fused dot
@@ -197,7 +203,8 @@ static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0, bo
 // in rumask.  Defect correction restarts BiCGstab there: new shadow residual,
 // p = v = 0 and the scalars of a first iteration.  (CG restarts through
 // beta = 0 at FIN_CG_RHO, so that the p update after the step sets p = r^.)
-static hipError_t reseed(wd_solver* h, bool first, const Field& r64) {
+// n_map: as for true_residual (CG's M_hat^dag r launches).
+static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map = 0) {
   const Geom& g = h->geom;
   const wd_prec P = h->prm.inner;
   if (h->kind == WD_SOLVER_BICGSTAB) {
@@ -212,7 +219,7 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64) {
   } else {
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
     // normal-equation residual M_hat^dag r in FP64
-    WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask));
+    WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask, n_map));
     WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->rn, nullptr, h->rumask, h->partials, h->s));
     WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask, false));
     if (first) WD_TRY(blas_convert(g, P, h->p, P, h->rh, h->rumask, h->s));  // p = r^
@@ -233,7 +240,7 @@ static hipError_t reliable_update(wd_solver* h) {
   if (h->kind == WD_SOLVER_BICGSTAB && !h->prm.restart && h->prm.inner != WD_FP64)
     return true_residual(h, h->rumask, n, true);  // r = b - M x; r^ = r, x^ = 0 in the same pass
   WD_TRY(true_residual(h, h->rumask, n));  // r = b - M x
-  WD_TRY(reseed(h, false, h->r));          // r^ = r, x^ = 0
+  WD_TRY(reseed(h, false, h->r, n));       // r^ = r (CG: M_hat^dag r), x^ = 0
   return hipSuccess;
 }
 
