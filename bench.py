@@ -44,8 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector FMA rate without packed-FP32 instructions (which this build does
-# not use): 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
+# FP32 vector FMA rate without packed-FP32 instructions (the library is compiled
+# without them): 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 DIMS = (48, 48, 48, 96)
 KAPPA = 0.124
@@ -219,8 +219,8 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (--gpus must be 1)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no "
+                                   "multi-GPU path (--gpus must be 1)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
