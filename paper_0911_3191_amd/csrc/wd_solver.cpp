@@ -476,10 +476,10 @@ hipError_t solver_issue(wd_solver* h) {
   } else {
     e = iteration_body(h);
   }
+  // only the flags come back every iteration; the scalars are read when a
+  // breakdown is reported, at a reliable update and at the end
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->h_fl, h->fl, sizeof(int) * FL_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h->h_sc, h->sc, sizeof(double) * SC_COUNT * h->nrhs, hipMemcpyDeviceToHost, h->s);
   return e;
 }
 
@@ -488,6 +488,12 @@ hipError_t solver_issue(wd_solver* h) {
 wd_status solver_complete(wd_solver* h) {
   hipError_t e = hipStreamSynchronize(h->s);
   if (e != hipSuccess) return hip_fail(e, "solver iteration");
+  for (int k = 0; k < h->nrhs; ++k)
+    if (!h->done_rhs[k] && h->h_fl[k * FL_COUNT + FL_BREAK]) {
+      e = read_flags(h);  // the breakdown note quotes the scalars
+      if (e != hipSuccess) return hip_fail(e, "solver iteration");
+      break;
+    }
   {
     ++h->loops;
     bool any_ru = false;
