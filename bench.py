@@ -138,12 +138,13 @@ def other_configs(wd, torch, wdinputs, stream) -> dict:
     """8^4 plain FP64 BiCGstab to 1e-10; 24^3x32 Gaussian source by RU-BiCGstab
     with FP32, int16 and binary16 inner solvers against FP64 (eps 0.3, seed 2,
     kappa 0.124); 24^3x32 CG on 12 point sources in FP32 and binary16 storage
-    under hipGraph (eps 0.5, seed 3, kappa 0.1245).  Each solve runs once
-    untimed (launch shapes are tuned) and once timed."""
+    under hipGraph (eps 0.5, seed 3, kappa 0.1245).  These small solves read
+    the flags every 4 iterations (one graph of 4 iterations per host check).
+    Each solve runs once untimed (launch shapes are tuned) and once timed."""
     dev = torch.device("cuda:0")
 
     def timed(gauge, lat, kappa, b, solver, **kw):
-        p = wd.solve_params(maxiter=20000, use_graph=True, **kw)
+        p = wd.solve_params(maxiter=20000, use_graph=True, check_every=4, **kw)
         ws = wd.new_workspace(lat, p, solver)
         fn = wd.bicgstab_solve if solver == "bicgstab" else wd.cg_solve
         x = torch.zeros_like(b)

@@ -233,7 +233,12 @@ typedef struct {
   int32_t nrhs;        /* right-hand sides solved together, 1..64 (one multi-RHS dslash per hop) */
   int32_t use_graph;   /* 1: the iteration body is captured once as a hipGraph and replayed
                           (needs a non-NULL stream) */
-  int32_t check_every; /* reserved, must be 0 or 1 */
+  int32_t check_every; /* inner iterations launched (and, with use_graph, captured in one
+                          graph) between two reads of the per-RHS flags by the host, 0..64
+                          (0 and 1: every iteration).  An RHS that triggers a reliable
+                          update, converges or breaks down waits on the device for the
+                          rest of the batch, so results do not depend on it; maxiter is
+                          checked once per batch */
   int32_t x0_given;    /* reserved, must be 0 */
   int32_t restart;     /* 0: reliable updates (Algorithm 2), the Krylov space is kept across
                           updates.  1: defect correction (Algorithm 1): each update ends an
@@ -276,7 +281,8 @@ wd_status cg_solve(const wd_gauge *g, double kappa, double *x, const double *b,
 
 /* Step API for interleaving several solves (one stream each).  begin
  * validates, prepares the source and the first residual; step runs up to
- * n_iters iterations (each followed by its reliable update if triggered) and
+ * n_iters batches of check_every iterations (each batch followed by the
+ * reliable updates it triggered) and
  * sets *done when every RHS has converged, broken down or reached maxiter;
  * end reconstructs x, fills info[nrhs] and releases the handle. */
 wd_status wd_solver_begin(int32_t solver, const wd_gauge *g, double kappa, double *x,

@@ -166,11 +166,12 @@ SOLVER = {"bicgstab": WD_SOLVER_BICGSTAB, "cg": WD_SOLVER_CG}
 
 
 def solve_params(tol=1e-12, maxiter=10000, inner="fp64", delta=0.1, nrhs=1, use_graph=False,
-                 restart=False) -> SolveParams:
+                 restart=False, check_every=0) -> SolveParams:
     """restart=False: reliable updates (Algorithm 2); True: defect correction
-    (Algorithm 1) with inner tolerance delta."""
+    (Algorithm 1) with inner tolerance delta.  check_every: iterations per
+    read of the flags by the host (0 or 1: every iteration)."""
     return SolveParams(tol=tol, maxiter=maxiter, inner=prec_of(inner), delta=delta, nrhs=nrhs,
-                       use_graph=1 if use_graph else 0, check_every=0, x0_given=0,
+                       use_graph=1 if use_graph else 0, check_every=int(check_every), x0_given=0,
                        restart=1 if restart else 0)
 
 

@@ -346,7 +346,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       s[SC_MMAX] = sqrt(v[0]);
       f[FL_CONV] = (sqrt(v[0]) <= stop) ? 1 : 0;
       if (!isfinite(v[0])) f[FL_BREAK] = stage + 1;
-      if (f[FL_CONV] || f[FL_BREAK]) active[rhs] = 0;
+      // iteration resumes (an RHS that triggered the update was paused) unless done
+      active[rhs] = (f[FL_CONV] || f[FL_BREAK]) ? 0 : 1;
       // FL_RU stays as the iteration set it: the host counts the update from it
       rumask[rhs] = active[rhs];  // the residual is re-seeded only where iteration goes on
       break;
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       s[SC_MMAX] = sqrt(v[0]);
       f[FL_CONV] = (sqrt(v[0]) <= stop) ? 1 : 0;
       if (!isfinite(v[0])) f[FL_BREAK] = FIN_TRUE + 1;
-      if (f[FL_CONV] || f[FL_BREAK]) active[rhs] = 0;
+      active[rhs] = (f[FL_CONV] || f[FL_BREAK]) ? 0 : 1;
       rumask[rhs] = active[rhs];
       if (active[rhs]) {
         s[SC_R2] = v[1];
@@ -381,6 +382,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       break;
     }
     case FIN_BICG_ALPHA: {  // alpha = rho / <r~, v>
+      ++f[FL_ITERS];
       const cx<double> d = {v[0], v[1]};
       if (!(d.re * d.re + d.im * d.im > 0.0) || !isfinite(d.re) || !isfinite(d.im)) {
         f[FL_BREAK] = stage + 1;
@@ -428,6 +430,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       const int ru = (rn < fa.delta * s[SC_MMAX]) || (rn <= stop);
       f[FL_RU] = ru;
       rumask[rhs] = ru;
+      if (ru) active[rhs] = 0;  // paused until the host has run the update
       break;
     }
     case FIN_CG_INIT: {  // rho = |r^|^2 of the normal-equation residual; internal target
@@ -438,6 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       break;
     }
     case FIN_CG_ALPHA: {  // alpha = rho / |M p|^2
+      ++f[FL_ITERS];
       if (!(v[0] > 0.0) || !isfinite(v[0])) {
         f[FL_BREAK] = stage + 1;
         active[rhs] = 0;
@@ -461,6 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       const int ru = (rn < fa.delta * s[SC_MMAX]) || (rn <= s[SC_TOLN]);
       f[FL_RU] = ru;
       rumask[rhs] = ru;
+      if (ru) active[rhs] = 0;  // paused until the host has run the update
       break;
     }
     case FIN_CG_RHO: {  // after a reliable update: new |r^|^2, beta against the old rho

@@ -165,7 +165,9 @@ enum ScalarSlot {
   SC_BNORM = 14,   // |b| of the caller's source (the solve runs on b / |b|)
   SC_COUNT = 16
 };
-enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_COUNT = 4 };
+// FL_ITERS counts the inner iterations an RHS has started, on the device, so
+// that several iterations can run between two reads of the flags by the host.
+enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_ITERS = 3, FL_COUNT = 4 };
 enum FinStage {
   FIN_B2_FIRST, FIN_B2_ADD, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
   FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO,

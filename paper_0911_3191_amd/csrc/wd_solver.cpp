@@ -80,6 +80,7 @@ struct wd_solver {
   double* h_sc;    // pinned host copy of the scalars
   std::vector<int> iters, rus, status, done_rhs;
   std::string note;  // breakdown details for wd_last_error
+  int per_check;     // inner iterations launched between two reads of the flags
   int loops;
   bool finished;
   hipGraph_t graph;
@@ -158,6 +159,9 @@ static hipError_t iteration_body(wd_solver* h) {
     WD_TRY(mhat_into(h, P, h->v, h->t, h->to, 1, DOT_NONE, nullptr, act));
     WD_TRY(blas_cg_xr(g, P, h->xh, h->rh, h->p, h->v, h->sc, act, h->partials, h->s));
     WD_TRY(fin(h, FIN_CG_ITER, act, false));
+    // p = r^ + beta p where iteration goes on; an RHS that triggered a
+    // reliable update is paused and takes this step after the update
+    WD_TRY(blas_cg_p(g, P, h->p, h->rh, h->sc, act, h->s));
   }
   return hipSuccess;
 }
@@ -325,7 +329,7 @@ wd_status validate(int kind, const wd_gauge* g, double kappa, const void* x, con
   if (prm->nrhs < 1 || prm->nrhs > 64) return fail(WD_EINVAL, "nrhs must be in [1, 64]");
   if (prm->inner < WD_FP64 || prm->inner > WD_HALF_F16) return fail(WD_EINVAL, "unknown inner precision");
   if (prm->x0_given != 0) return fail(WD_EUNSUPPORTED, "x0_given is not supported");
-  if (prm->check_every < 0 || prm->check_every > 1) return fail(WD_EINVAL, "check_every must be 0 or 1");
+  if (prm->check_every < 0 || prm->check_every > 64) return fail(WD_EINVAL, "check_every must be in [0, 64]");
   if (prm->restart < 0 || prm->restart > 1) return fail(WD_EINVAL, "restart must be 0 or 1");
   if (prm->restart == 1 && !(prm->delta > 0.0))
     return fail(WD_EINVAL, "defect correction needs an inner tolerance delta > 0");
@@ -409,6 +413,7 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   h->done_rhs.assign(h->nrhs, 0);
   h->graph_ready = false;
   h->finished = false;
+  h->per_check = prm->check_every > 1 ? prm->check_every : 1;
   h->loops = 0;
   h->t0 = std::chrono::steady_clock::now();
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->h_fl), sizeof(int) * (FL_COUNT + 1) * h->nrhs);
@@ -458,14 +463,23 @@ bool solver_finished(wd_solver* h) {
   return h->finished;
 }
 
-// Launch one iteration and the asynchronous copy of its flags; returns at once.
+// Launch per_check iterations and the asynchronous copy of their flags;
+// returns at once.  An RHS that triggers a reliable update, converges or
+// breaks down is paused on the device (its active flag), so the iterations
+// after it in the same batch leave it untouched and the result does not
+// depend on per_check.
+static hipError_t issue_body(wd_solver* h) {
+  for (int i = 0; i < h->per_check; ++i) WD_TRY(iteration_body(h));
+  return hipSuccess;
+}
+
 hipError_t solver_issue(wd_solver* h) {
   hipError_t e = hipSuccess;
   if (h->prm.use_graph && h->s) {
     if (!h->graph_ready) {
       e = hipStreamBeginCapture(h->s, hipStreamCaptureModeRelaxed);
       if (e == hipSuccess) {
-        hipError_t eb = iteration_body(h);
+        hipError_t eb = issue_body(h);
         e = hipStreamEndCapture(h->s, &h->graph);
         if (eb != hipSuccess) e = eb;
       }
@@ -474,7 +488,7 @@ hipError_t solver_issue(wd_solver* h) {
     }
     if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->s);
   } else {
-    e = iteration_body(h);
+    e = issue_body(h);
   }
   // only the flags come back every iteration; the scalars are read when a
   // breakdown is reported, at a reliable update and at the end
@@ -483,8 +497,10 @@ hipError_t solver_issue(wd_solver* h) {
   return e;
 }
 
-// Wait for the issued iteration, account for it, run the reliable update if
-// one was triggered and (CG) the search-direction update.
+// Wait for the issued iterations, account for them, and run the reliable
+// update of the RHS that triggered one (CG: then their search-direction
+// update).  Iterations are counted on the device (FL_ITERS); a reliable
+// update counts as one more (k + l).
 wd_status solver_complete(wd_solver* h) {
   hipError_t e = hipStreamSynchronize(h->s);
   if (e != hipSuccess) return hip_fail(e, "solver iteration");
@@ -495,11 +511,11 @@ wd_status solver_complete(wd_solver* h) {
       break;
     }
   {
-    ++h->loops;
+    h->loops += h->per_check;
     bool any_ru = false;
     for (int k = 0; k < h->nrhs; ++k) {
       if (h->done_rhs[k]) continue;
-      ++h->iters[k];
+      h->iters[k] = h->h_fl[k * FL_COUNT + FL_ITERS] + h->rus[k];
       if (h->h_fl[k * FL_COUNT + FL_BREAK]) {
         h->done_rhs[k] = 1;
         h->status[k] = WD_EBREAKDOWN;
@@ -515,8 +531,8 @@ wd_status solver_complete(wd_solver* h) {
       ++h->loops;
       for (int k = 0; k < h->nrhs; ++k) {
         if (h->done_rhs[k] || !h->h_fl[k * FL_COUNT + FL_RU]) continue;
-        ++h->iters[k];
         ++h->rus[k];
+        h->iters[k] = h->h_fl[k * FL_COUNT + FL_ITERS] + h->rus[k];
         if (h->h_fl[k * FL_COUNT + FL_CONV]) {
           h->done_rhs[k] = 1;
           h->status[k] = WD_OK;
@@ -526,11 +542,11 @@ wd_status solver_complete(wd_solver* h) {
           note_breakdown(h, k);
         }
       }
-    }
-    if (h->kind == WD_SOLVER_CG) {
-      // p = r^ + beta p for the RHS still iterating (after any reliable update)
-      e = blas_cg_p(h->geom, h->prm.inner, h->p, h->rh, h->sc, h->active, h->s);
-      if (e != hipSuccess) return hip_fail(e, "cg p update");
+      if (h->kind == WD_SOLVER_CG) {
+        // p = r^ + beta p for the updated RHS that iterate on (rumask)
+        e = blas_cg_p(h->geom, h->prm.inner, h->p, h->rh, h->sc, h->rumask, h->s);
+        if (e != hipSuccess) return hip_fail(e, "cg p update");
+      }
     }
   }
   solver_finished(h);

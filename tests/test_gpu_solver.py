@@ -108,6 +108,43 @@ def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone(solver):
             assert info1["reliable_updates"] == infos[k]["reliable_updates"]
 
 
+@pytest.mark.parametrize("solver,restart,use_graph", [("bicgstab", False, False), ("bicgstab", False, True),
+                                                       ("cg", False, False), ("cg", False, True),
+                                                       ("bicgstab", True, True)])
+def test_iterations_between_flag_reads_do_not_change_the_result(solver, restart, use_graph):
+    """check_every = 3 runs three iterations (one graph) between two reads of
+    the flags by the host.  An RHS that triggers a reliable update (or, with
+    restart, ends an inner solve) waits on the device for the rest of the
+    batch, so x and the iteration and update counts equal those of a read
+    after every iteration."""
+    dims, kappa = (8, 4, 8, 6), 0.124
+    U = wdinputs.gauge_random(dims, 0.4, 13)
+    s = Setup(dims, U)
+    bs = wdinputs.spinor_gaussian(dims, 14, nrhs=5)
+    bs[1] = 0.0
+    bs[1][0, 0, 0, 0, 2, 1, 0] = 1.0
+    bs[3] = bs[3] * np.linspace(0.01, 3.0, bs[3].shape[0])[:, None, None, None, None, None, None]
+    kw = dict(tol=1e-12, inner="f16", delta=0.1, nrhs=5, use_graph=use_graph, restart=restart)
+    st1, x1, i1 = run(s, solver, bs, kappa, **kw)
+    st3, x3, i3 = run(s, solver, bs, kappa, check_every=3, **kw)
+    assert st1 == st3 == wd.WD_OK
+    assert np.array_equal(x1, x3)
+    for k in range(5):
+        assert i1[k]["iters"] == i3[k]["iters"], k
+        assert i1[k]["reliable_updates"] == i3[k]["reliable_updates"], k
+        assert oracle.true_relres(dims, U, kappa, bs[k], x3[k]) <= 1e-12
+
+
+def test_check_every_out_of_range_is_refused():
+    dims = (4, 4, 4, 4)
+    s = Setup(dims, wdinputs.gauge_random(dims, 0.3, 3))
+    bt = torch.from_numpy(wdinputs.spinor_gaussian(dims, 4)).to(DEV)
+    x = torch.zeros_like(bt)
+    ws = wd.new_workspace(s.lat, wd.solve_params(tol=1e-10), "bicgstab")
+    with pytest.raises(wd.WDError, match="check_every"):
+        wd.bicgstab_solve(s.gauge, 0.12, x, bt, wd.solve_params(tol=1e-10, check_every=65), ws)
+
+
 @pytest.mark.parametrize("shape", ["3,0,2,1,0,0,0", "4,1,2,0,0,0,0", "1,1,2,0,0,0,1"])
 def test_batch_under_any_launch_shape_equals_each_rhs_alone(shape, monkeypatch):
     """Launches with a fused dot product keep one sub-slab, so their partial
