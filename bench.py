@@ -473,12 +473,12 @@ def main():
         fields = make_fields(inner=inner)
         log(f"serving fields built in {time.time() - t3:.1f}s")
         serve = serve_stream(fields, n_requests=args.serve_requests, rate=20.0, seed=7, max_slots=16,
-                             inner=inner, log=log)
+                             inner=inner, log=log, check_every=2)
         # the same stream with the arena cut to about twice the largest footprint,
         # so that admission by HBM footprint binds
         tight = 2 * max(serve["footprint_bytes"].values()) + 4096
         serve_tight = serve_stream(fields, n_requests=max(args.serve_requests // 3, 20), rate=20.0, seed=8,
-                                   arena_bytes=tight, max_slots=16, inner=inner, log=log)
+                                   arena_bytes=tight, max_slots=16, inner=inner, log=log, check_every=2)
         serve["budget_2x_largest"] = {k: serve_tight[k] for k in
                                       ("requests", "arena_bytes", "p50_ms", "p99_ms", "solves_per_s",
                                        "max_in_flight", "max_queued")}

@@ -103,7 +103,7 @@ def gaussian_source(dims, seed: int, device="cuda"):
 
 def serve_stream(fields, n_requests=600, rate=20.0, seed=7, arena_bytes=None, max_slots=16,
                  iters_per_pump=1, inner="f16", delta=0.1, tol=1e-12, kappa_range=(0.120, 0.1245),
-                 log=None) -> dict:
+                 log=None, check_every=0) -> dict:
     """Poisson arrivals (exponential gaps of mean 1/rate, seeded) of single-RHS
     RU-BiCGstab solves: lattice size uniform over the sizes in `fields`, then
     a field of that size uniform, kappa uniform in kappa_range, Gaussian source
@@ -120,7 +120,8 @@ def serve_stream(fields, n_requests=600, rate=20.0, seed=7, arena_bytes=None, ma
         d = sizes[rng.integers(len(sizes))]
         f = by_size[d][rng.integers(len(by_size[d]))]
         choice.append((f, float(rng.uniform(*kappa_range))))
-    prm = solve_params(tol=tol, maxiter=20000, inner=inner, delta=delta, nrhs=1, use_graph=True)
+    prm = solve_params(tol=tol, maxiter=20000, inner=inner, delta=delta, nrhs=1, use_graph=True,
+                       check_every=check_every)
     need = {d: wd_solve_workspace_bytes(by_size[d][0][1], prm, "bicgstab") for d in sizes}
     if arena_bytes is None:
         free, _ = torch.cuda.mem_get_info()
