@@ -45,8 +45,9 @@ def requests(setups, n, seed):
     return reqs
 
 
-def params_of(inner, use_graph=True):
-    return wd.solve_params(tol=1e-12, maxiter=5000, inner=inner, delta=0.1, nrhs=1, use_graph=use_graph)
+def params_of(inner, use_graph=True, check_every=0):
+    return wd.solve_params(tol=1e-12, maxiter=5000, inner=inner, delta=0.1, nrhs=1, use_graph=use_graph,
+                           check_every=check_every)
 
 
 def solve_alone(s, solver, kappa, inner, b):
@@ -62,14 +63,14 @@ def solve_alone(s, solver, kappa, inner, b):
     return st, x.cpu().numpy(), info[0]
 
 
-def run_mix(reqs, arena_bytes, max_slots, iters_per_pump=1):
+def run_mix(reqs, arena_bytes, max_slots, iters_per_pump=1, check_every=0):
     srv = Server(arena_bytes, max_slots=max_slots, iters_per_pump=iters_per_pump)
     ids, keep = [], []
     for s, solver, kappa, inner, b in reqs:
         bt = torch.from_numpy(np.ascontiguousarray(b)).to(DEV)
         x = torch.zeros_like(bt)
         torch.cuda.synchronize()
-        ids.append(srv.submit(solver, s.gauge, kappa, x, bt, params_of(inner)))
+        ids.append(srv.submit(solver, s.gauge, kappa, x, bt, params_of(inner, check_every=check_every)))
         keep.append(x)
     results = {}
     trace = []
@@ -102,6 +103,22 @@ def test_each_result_is_the_same_alone_and_in_the_mix(setups):
         assert np.array_equal(x, x_a), f"request {k}: result differs from the same solve alone"
         s, _, kappa, _, b = reqs[k]
         assert oracle.true_relres(s.dims, s.U, kappa, b[0], x[0]) <= 1e-12
+
+
+def test_mix_with_several_iterations_per_flag_read_equals_each_solve_alone(setups):
+    """Solves that read their flags every 3 iterations, interleaved by the
+    scheduler, give the bits and iteration counts of the same solves alone
+    reading them every iteration."""
+    reqs = requests(setups, 6, 5)
+    alone = [solve_alone(*r) for r in reqs]
+    need = max(wd.wd_solve_workspace_bytes(r[0].lat, params_of(r[3]), r[1]) for r in reqs)
+    res, xs, _ = run_mix(reqs, arena_bytes=16 * need, max_slots=4, check_every=3)
+    for k, ((st, info), x) in enumerate(zip(res, xs)):
+        st_a, x_a, info_a = alone[k]
+        assert st == st_a == wd.WD_OK, k
+        assert info[0]["iters"] == info_a["iters"], k
+        assert info[0]["reliable_updates"] == info_a["reliable_updates"], k
+        assert np.array_equal(x, x_a), f"request {k}"
 
 
 def test_admission_binds_on_the_arena_budget(setups):
