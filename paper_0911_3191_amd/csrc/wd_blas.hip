@@ -358,6 +358,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
       s[SC_RHO + 1] = v[2];
       break;
     }
+    case FIN_TRUE_INIT:   // the same with a new shadow residual: a first iteration follows
     case FIN_TRUE_RHO: {  // both, from the residual dslash that re-encoded r itself
       s[SC_RTRUE2] = v[0];
       s[SC_MMAX] = sqrt(v[0]);
@@ -369,6 +370,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
         s[SC_R2] = v[1];
         s[SC_RHO] = v[2];
         s[SC_RHO + 1] = v[3];
+        if (stage == FIN_TRUE_INIT) {
+          s[SC_RHOP] = 1.0; s[SC_RHOP + 1] = 0.0;
+          s[SC_ALPHA] = 1.0; s[SC_ALPHA + 1] = 0.0;
+          s[SC_OMEGA] = 1.0; s[SC_OMEGA + 1] = 0.0;
+        }
       }
       break;
     }

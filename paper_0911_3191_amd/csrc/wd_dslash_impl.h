@@ -745,13 +745,15 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_OO: |out|^2                  (CG |M p|^2)
 //   DOT_RES: out = y - (x + a * D in), |out|^2 (FP64 residual b_hat - M_hat x)
 //   DOT_RES_ENC: r = y - (x + a * D in) re-encoded in format S2 into enc.rh
-//     (out is not written), enc.xh = 0; |r|^2, |enc(r)|^2, <enc.rt, enc(r)>
+//     (out is not written), enc.xh = 0, with enc.set_rt also enc.rt = enc(r);
+//     |r|^2, |enc(r)|^2, <enc.rt, enc(r)>
 // Right-hand sides whose active flag in `sel` is 0 are skipped; with g.mapped,
 // `sel` instead lists the g.nrhs right-hand sides to process, packed into the
 // RHS slots of as few groups as they fill.  BASIS: spin basis of in, out, x
 // and y (kBasisDR or kBasisUK); the links do not depend on it.
 struct EncView {
   FieldView rh, xh, rt;
+  int set_rt;
 };
 
 template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS, class S2 = S>
@@ -906,6 +908,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
           }
         store_spinor<S2>(enc.rh, rhs[k], cb, e);
         store_spinor<S2>(enc.xh, rhs[k], cb, z);
+        if (enc.set_rt) store_spinor<S2>(enc.rt, rhs[k], cb, e);
         // the dots see the stored (re-encoded) residual
         load_spinor<S2>(enc.rh, rhs[k], cb, e);
         load_spinor<S2>(enc.rt, rhs[k], cb, t);
@@ -1100,7 +1103,7 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   using R = typename S::real;
   const R ar = static_cast<R>(d.a);
   const int dot = d.xpay ? d.dot : DOT_NONE;
-  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt)};
+  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt), d.enc_set_rt};
   size_t lds = lds_for(c.wgs);
   if constexpr (LDS) lds = std::max(lds, lds_stage_bytes(g, NR));
   if (d.dagger) {

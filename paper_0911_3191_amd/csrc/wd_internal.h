@@ -63,8 +63,10 @@ constexpr int kMaxDotHost = 4;  // doubles per partial record
 // DOT_RES (FP64 only): out = y - (xpay + a D in), the residual of a reliable
 // update, with |out|^2 partials.  DOT_RES_ENC (FP64, UKQCD basis): the same
 // residual r is not stored in FP64 but re-encoded straight into the inner
-// solver's fields: enc_rh = enc(r), enc_xh = 0, partials |r|^2, |enc(r)|^2,
-// <enc_rt, enc(r)> (the last two on the stored values).
+// solver's fields: enc_rh = enc(r), enc_xh = 0 (with enc_set_rt also the new
+// shadow residual enc_rt = enc(r), as defect correction restarts from it),
+// partials |r|^2, |enc(r)|^2, <enc_rt, enc(r)> (the last two on the stored
+// values).
 enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4, DOT_RES_ENC = 5 };
 
 // Full argument set of one dslash launch.  out = D in, or, with xpay set,
@@ -95,6 +97,7 @@ struct DslashArgs {
   const Field* enc_rh = nullptr;
   const Field* enc_xh = nullptr;
   const Field* enc_rt = nullptr;
+  int enc_set_rt = 0;
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 
@@ -171,7 +174,8 @@ enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_ITERS = 3, FL_COUNT = 4
 enum FinStage {
   FIN_B2_FIRST, FIN_B2_ADD, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
   FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO,
-  FIN_TRUE_RHO  // FIN_TRUE on v[0], then FIN_RHO on v[1..3] where iteration goes on
+  FIN_TRUE_RHO,  // FIN_TRUE on v[0], then FIN_RHO on v[1..3] where iteration goes on
+  FIN_TRUE_INIT  // FIN_TRUE on v[0], then FIN_BICG_INIT on v[1..3] where iteration goes on
 };
 
 hipError_t blas_bicg_p(const Geom& g, wd_prec pr, Field p, Field r, Field v, const double* sc,

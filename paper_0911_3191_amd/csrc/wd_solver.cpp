@@ -174,6 +174,8 @@ static hipError_t iteration_body(wd_solver* h) {
 // reencode (BiCGstab with reliable updates) the second dslash does not store
 // r in FP64 but re-encodes it into r^ itself, zeroes x^ and returns
 // <r~, r^> and |r^|^2 beside |r|^2: the whole re-seed of the inner solver.
+// With restart (defect correction) the same pass also writes the new shadow
+// residual r~ = r^, and the scalars are those of a first iteration.
 static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0, bool reencode = false) {
   DslashArgs d;
   d.out = h->to64;
@@ -198,8 +200,13 @@ static hipError_t true_residual(wd_solver* h, const int* mask, int n_map = 0, bo
   d.enc_rh = &h->rh;
   d.enc_xh = &h->xh;
   d.enc_rt = &h->rt;
+  d.enc_set_rt = h->prm.restart;
   WD_TRY(launch_dslash_ex(h->g, WD_FP64, d, h->s));
-  WD_TRY(fin(h, reencode ? FIN_TRUE_RHO : FIN_TRUE, mask, true));
+  WD_TRY(fin(h, !reencode ? FIN_TRUE : (h->prm.restart ? FIN_TRUE_INIT : FIN_TRUE_RHO), mask, true));
+  if (reencode && h->prm.restart) {  // p = v = 0 where the restarted solve goes on
+    WD_TRY(blas_zero(h->geom, h->prm.inner, h->p, h->rumask, h->s));
+    WD_TRY(blas_zero(h->geom, h->prm.inner, h->v, h->rumask, h->s));
+  }
   return hipSuccess;
 }
 
@@ -241,7 +248,7 @@ static hipError_t reliable_update(wd_solver* h) {
   else
     n = 0;  // every RHS (or, defensively, none listed): the mask alone
   WD_TRY(blas_accum(h->geom, h->prm.inner, h->x, h->xh, h->rumask, h->s));  // x += x^
-  if (h->kind == WD_SOLVER_BICGSTAB && !h->prm.restart && h->prm.inner != WD_FP64)
+  if (h->kind == WD_SOLVER_BICGSTAB && h->prm.inner != WD_FP64)
     return true_residual(h, h->rumask, n, true);  // r = b - M x; r^ = r, x^ = 0 in the same pass
   WD_TRY(true_residual(h, h->rumask, n));  // r = b - M x
   WD_TRY(reseed(h, false, h->r, n));       // r^ = r (CG: M_hat^dag r), x^ = 0

@@ -83,13 +83,13 @@ def test_multi_rhs_batch_equals_each_rhs_alone():
             assert info1["iters"] == infos[k]["iters"]
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "cg"])
-def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone(solver):
+@pytest.mark.parametrize("solver,restart", [("bicgstab", False), ("cg", False), ("bicgstab", True)])
+def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone(solver, restart):
     """Five RHS of different structure reach their reliable updates at different
     iterations, so the updates run on packed subsets of the batch (BiCGstab
     re-encodes the residual inside the FP64 dslash; CG forms M_hat^dag r on the
-    same subset): every RHS must still come out bit for bit as when solved
-    alone, and solve the system."""
+    same subset; defect correction also restarts there): every RHS must still
+    come out bit for bit as when solved alone, and solve the system."""
     dims, kappa = (8, 4, 8, 6), 0.124
     U = wdinputs.gauge_random(dims, 0.4, 13)
     s = Setup(dims, U)
@@ -98,11 +98,11 @@ def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone(solver):
     bs[1][0, 0, 0, 0, 2, 1, 0] = 1.0                 # a point source
     bs[3] = bs[3] * np.linspace(0.01, 3.0, bs[3].shape[0])[:, None, None, None, None, None, None]
     for inner in ("f16", "fp32"):
-        st, xb, infos = run(s, solver, bs, kappa, tol=1e-12, inner=inner, delta=0.1, nrhs=5)
+        st, xb, infos = run(s, solver, bs, kappa, tol=1e-12, inner=inner, delta=0.1, nrhs=5, restart=restart)
         assert st == wd.WD_OK
         for k in range(5):
             assert oracle.true_relres(dims, U, kappa, bs[k], xb[k]) <= 1e-12
-            st1, x1, info1 = run(s, solver, bs[k], kappa, tol=1e-12, inner=inner, delta=0.1)
+            st1, x1, info1 = run(s, solver, bs[k], kappa, tol=1e-12, inner=inner, delta=0.1, restart=restart)
             assert np.array_equal(x1, xb[k]), f"{inner} rhs {k}"
             assert info1["iters"] == infos[k]["iters"]
             assert info1["reliable_updates"] == infos[k]["reliable_updates"]
