@@ -26,9 +26,17 @@ Reported:
                    practical ceiling beside the nominal 8 TB/s
   dslash_rhs_scan  (--rhs-scan) dslash time against the RHS count per launch
   other_configs    time to solution on the smaller lattices, mixed vs FP64
+  next1            8-real links and temporal gauge (Section 4.3, Appendix A.2):
+                   the dslash in every format with 1 and 12 RHS on recon-8,
+                   temporal-gauge recon-12 and temporal-gauge recon-8 handles,
+                   and the 12-RHS solve on the temporal-gauge recon-8 handle
   serve            the Poisson serving run (latency percentiles, solves/s)
   cpu_baseline     the FP64 oracle's own BiCGstab on source 0, stopped after one
-                   and after two iterations: the difference is one iteration
+                   and after two iterations: the difference is one iteration;
+                   the same CPU leg has the oracle compute the FP64 true
+                   residual of every GPU solution of the step, of the FP64
+                   reference, of sampled temporal-gauge solutions and of every
+                   10th served request (oracle_check)
 """
 from __future__ import annotations
 
@@ -78,6 +86,15 @@ def dslash_bytes(prec: str, nrhs: int, xpay: int = 0) -> int:
     """Per output site: 8 links once per launch, nrhs input and output spinors
     (+ xpay extra spinor reads per RHS)."""
     return 8 * LINK_B[prec] + nrhs * SPINOR_B[prec] * (2 + xpay)
+
+
+def dslash_bytes_links(prec: str, nrhs: int, recon: int, temporal: bool, lt: int) -> float:
+    """As dslash_bytes, for recon-12 or recon-8 links (Appendix A), optionally
+    in temporal gauge (Section 4.3: the two time links of a site are read only
+    where they cross the last time slice, 2 of every lt sites)."""
+    per_link = LINK_B[prec] * recon // 12
+    links = 6 + (2.0 / lt if temporal else 2)
+    return links * per_link + nrhs * SPINOR_B[prec] * 2
 
 
 def bicgstab_iter_bytes(prec: str, nrhs: int) -> int:
@@ -191,6 +208,131 @@ def other_configs(wd, torch, wdinputs, stream) -> dict:
     return out
 
 
+def time_dslash(wd, torch, gauge, lat, prec: str, n: int, gsrc, stream, reps: int) -> float:
+    """Seconds per launch of the n-RHS dslash (UKQCD-basis fields, as in the
+    solvers) on `gauge`, HIP events on the launch stream."""
+    UK = wd.WD_BASIS_UKQCD
+    fi = wd.new_field(lat, prec, n)
+    fo = wd.new_field(lat, prec, n)
+    with torch.cuda.stream(stream):
+        wd.wd_spinor_encode_basis(lat, prec, n, UK, fi, gsrc[0:n], stream)
+        for _ in range(3):
+            wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+        e1.record(stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del fi, fo
+    return t
+
+
+def measure_next1(wd, torch, args, lat, dims, U, gauge, gsrc, b, stream):
+    """8-real links and temporal gauge fixing (Section 4.3, Appendix A.2): the
+    dslash on recon-12, recon-8, temporal-gauge recon-12 and temporal-gauge
+    recon-8 handles of the same field, in every format with 1 and 12 RHS
+    (algorithmic bytes from dslash_bytes_links), and the step's 12-RHS solve
+    on the temporal-gauge recon-8 handle: sources rotated by the gauge
+    transformation g, solutions rotated back by g^dagger, so they solve the
+    original system (checked by the oracle in the CPU leg).  Returns the
+    report and host copies of RHS 0, 5 and 11 of that solve."""
+    dev = torch.device("cuda:0")
+    Vh = int(np.prod(dims)) // 2
+    lt = dims[3]
+    precs = ("fp64", "fp32", "i16", "f16")
+    U_dev = torch.from_numpy(U).to(dev)
+    handles = {"recon12": (gauge, 12, False), "recon8": (wd.Gauge(lat, U_dev, precs, recon=8), 8, False)}
+    Ug, gmat = wd.gauge_fix_temporal(lat, U_dev)
+    del U_dev
+    handles["recon12_temporal"] = (wd.Gauge(lat, Ug, precs, recon=12, temporal=True), 12, True)
+    handles["recon8_temporal"] = (wd.Gauge(lat, Ug, precs, recon=8, temporal=True), 8, True)
+    del Ug
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    dsl = {}
+    for name, (g, recon, tg) in handles.items():
+        rows = {}
+        for prec in precs:
+            row = {}
+            for n in (1, NRHS):
+                t = time_dslash(wd, torch, g, lat, prec, n, gsrc, stream, args.dslash_reps)
+                per_site = dslash_bytes_links(prec, n, recon, tg, lt)
+                gbs = per_site * Vh / t / 1e9
+                row[str(n)] = {"us": round(t * 1e6, 1), "alg_B_per_site": round(per_site, 2),
+                               "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "gflops": round(1320 * Vh * n / t / 1e9, 1)}
+            rows[prec] = row
+        dsl[name] = rows
+        log(f"next1 dslash {name}: {rows}")
+    # the step's solve on the temporal-gauge recon-8 handle
+    g8t = handles["recon8_temporal"][0]
+    p = wd.solve_params(tol=1e-12, maxiter=20000, inner=args.inner, delta=0.1, nrhs=NRHS, use_graph=True)
+    ws = wd.new_workspace(lat, p, "bicgstab")
+    bt = torch.empty_like(b)
+    xt = torch.zeros_like(b)
+    wd.wd_gauge_rotate_spinor(lat, gmat, bt, b, NRHS, False)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):  # untimed: tunes the recon-8 temporal-gauge launch shapes
+        wd.bicgstab_solve(g8t, KAPPA, xt, bt, p, ws, stream)
+    xt.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        st, infos = wd.bicgstab_solve(g8t, KAPPA, xt, bt, p, ws, stream)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    wd.wd_gauge_rotate_spinor(lat, gmat, xt, xt, NRHS, True)
+    torch.cuda.synchronize()
+    kept = [(k, xt[k].cpu().numpy()) for k in (0, 5, NRHS - 1)] if not args.no_oracle_check else None
+    solve = {"batch_s": round(t_solve, 3), "status": st, "iters_max": max(i["iters"] for i in infos),
+             "reliable_updates_max": max(i["reliable_updates"] for i in infos),
+             "true_rel_resid_max": max(i["true_rel_resid"] for i in infos)}
+    log(f"next1 solve (temporal gauge, recon 8): {solve}")
+    del ws, bt, xt, gmat, handles, g8t
+    torch.cuda.empty_cache()
+    return {"dslash": dsl, "solve_recon8_temporal": solve,
+            "bytes_model": "per site: links (8, or 6 + 2/Lt in temporal gauge) x (12 or 8 reals) + "
+                           "nrhs x (input + output spinor)"}, kept
+
+
+def oracle_checks(oracle, dims, U, x_host, x64_host, xtg_host, serve_kept, serve_fields) -> dict:
+    """The FP64 oracle's true residual ||b - (1 - kappa D) x|| / ||b|| of the
+    GPU solutions kept from this run (Section 5.3: the stopping contract of
+    Algorithm 2 is a true residual of 1e-12)."""
+    import wdinputs
+    V = int(np.prod(dims))
+    t0 = time.perf_counter()
+    bsrc = np.zeros((V, 4, 3, 2))
+    out = {}
+
+    def point(k):
+        bsrc[:] = 0.0
+        bsrc[0, k // 3, k % 3, 0] = 1.0
+        return bsrc
+
+    if x_host is not None:
+        res = [oracle.true_relres(dims, U, KAPPA, point(k), x_host[k]) for k in range(len(x_host))]
+        out["step_per_rhs"] = [float(f"{r:.3e}") for r in res]
+        out["step_max"] = max(res)
+    if x64_host is not None:
+        out["fp64_reference"] = oracle.true_relres(dims, U, KAPPA, point(0), x64_host)
+    if xtg_host is not None:
+        res = {k: oracle.true_relres(dims, U, KAPPA, point(k), xk) for k, xk in xtg_host}
+        out["recon8_temporal_sampled"] = {str(k): float(f"{r:.3e}") for k, r in res.items()}
+        out["recon8_temporal_max"] = max(res.values())
+    if serve_kept and serve_fields is not None:
+        res = []
+        for k, fk, kappa, seed, x in serve_kept:
+            d, Uf = serve_fields[fk]
+            res.append(oracle.true_relres(d, Uf, kappa, wdinputs.spinor_gaussian(d, seed), x[0]))
+        out["serve_checked"] = len(res)
+        out["serve_max"] = max(res)
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,8 +345,12 @@ def parse():
     ap.add_argument("--no-defect-correction", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the Poisson serving run (0: skip it)")
+    ap.add_argument("--no-next1", action="store_true",
+                    help="skip the 8-real / temporal-gauge measurements")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle's true residuals of the GPU solutions")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter scaling)")
     ap.add_argument("--rhs-scan", action="store_true",
@@ -275,6 +421,8 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
     infos = all_infos[-1]
+    # the step's solutions, kept on the host for the oracle's check (CPU leg)
+    x_host = None if args.no_oracle_check else [x[k].cpu().numpy() for k in range(NRHS)]
     iters = [inf["iters"] for inf in infos]
     rus = [inf["reliable_updates"] for inf in infos]
     worst_res = max(inf["true_rel_resid"] for inf in infos)
@@ -306,6 +454,7 @@ def main():
 
     # ---- FP64 single-RHS reference solve (same source 0) ----
     fp64 = None
+    x64_host = None
     if not args.no_fp64_reference:
         p64 = wd.solve_params(tol=1e-12, maxiter=20000, inner="fp64", delta=0.0, nrhs=1, use_graph=True)
         ws = None
@@ -324,6 +473,7 @@ def main():
         t64 = time.perf_counter() - t1
         fp64 = {"seconds": t64, "iters": inf64[0]["iters"], "true_rel_resid": inf64[0]["true_rel_resid"],
                 "status": st64}
+        x64_host = None if args.no_oracle_check else x0[0].cpu().numpy()
         log(f"fp64 reference: {t64:.3f}s iters {inf64[0]['iters']}")
         del ws64
         # the same single source by the mixed solver (warmed once, then timed)
@@ -357,11 +507,11 @@ def main():
     with torch.cuda.stream(stream):
         wd.wd_spinor_encode_basis(lat, inner, NRHS, UK, fin, gsrc, stream)
         for _ in range(3):
-            wd.wilson_dslash_basis(gauge, fout, fin, 0, 0, inner, NRHS, UK, stream)
+            wd.wd_dslash_field_basis(gauge, fout, fin, 0, 0, inner, NRHS, UK, stream)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(args.dslash_reps):
-            wd.wilson_dslash_basis(gauge, fout, fin, 0, 0, inner, NRHS, UK, stream)
+            wd.wd_dslash_field_basis(gauge, fout, fin, 0, 0, inner, NRHS, UK, stream)
         ev1.record(stream)
     ev1.synchronize()
     t_dslash = ev0.elapsed_time(ev1) / args.dslash_reps * 1e-3
@@ -380,11 +530,11 @@ def main():
         with torch.cuda.stream(stream):
             wd.wd_spinor_encode_basis(lat, prec, 1, UK, fi, gsrc[0:1], stream)
             for _ in range(3):
-                wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, 1, UK, stream)
+                wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, 1, UK, stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(args.dslash_reps):
-                wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, 1, UK, stream)
+                wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, 1, UK, stream)
             e1.record(stream)
         e1.synchronize()
         t = e0.elapsed_time(e1) / args.dslash_reps * 1e-3
@@ -394,6 +544,10 @@ def main():
                        "paper_model_GB/s": round(PAPER_MODEL_B[prec] * Vh / t / 1e9, 1)}
         del fi, fo
     log(f"dslash table {table}")
+    next1 = None
+    xtg_host = None
+    if not args.no_next1:
+        next1, xtg_host = measure_next1(wd, torch, args, lat, dims, U, gauge, gsrc, b, stream)
     rhs_scan = None
     if args.rhs_scan:
         # cost of each added right-hand side in one launch (tuned shapes)
@@ -406,11 +560,11 @@ def main():
                 with torch.cuda.stream(stream):
                     wd.wd_spinor_encode_basis(lat, prec, n, UK, fi, gsrc[0:n], stream)
                     for _ in range(3):
-                        wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+                        wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
                     for _ in range(args.dslash_reps):
-                        wd.wilson_dslash_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
+                        wd.wd_dslash_field_basis(gauge, fo, fi, 0, 0, prec, n, UK, stream)
                     e1.record(stream)
                 e1.synchronize()
                 t = e0.elapsed_time(e1) / args.dslash_reps * 1e-3
@@ -465,24 +619,30 @@ def main():
 
     # ---- serving: Poisson arrivals over 8 resident fields of three lattice sizes ----
     serve = None
+    serve_kept, serve_fields_host = [], None
     if args.serve_requests > 0:
-        from paper_0911_3191_amd.serve import make_fields, serve_stream
+        from paper_0911_3191_amd.serve import make_fields, serve_stream, source_pool
         b = x = ws = None
         torch.cuda.empty_cache()
         t3 = time.time()
-        fields = make_fields(inner=inner)
-        log(f"serving fields built in {time.time() - t3:.1f}s")
+        fields = make_fields(inner=inner, keep_host=not args.no_oracle_check)
+        pool = source_pool(sorted({f[0] for f in fields}))
+        log(f"serving fields and sources built in {time.time() - t3:.1f}s")
         serve = serve_stream(fields, n_requests=args.serve_requests, rate=20.0, seed=7, max_slots=16,
-                             inner=inner, log=log, check_every=2)
+                             inner=inner, log=log, check_every=2, pool=pool,
+                             keep_every=0 if args.no_oracle_check else 10)
+        serve_kept = serve.pop("kept", [])
         # the same stream with the arena cut to about twice the largest footprint,
         # so that admission by HBM footprint binds
         tight = 2 * max(serve["footprint_bytes"].values()) + 4096
         serve_tight = serve_stream(fields, n_requests=max(args.serve_requests // 3, 20), rate=20.0, seed=8,
-                                   arena_bytes=tight, max_slots=16, inner=inner, log=log, check_every=2)
+                                   arena_bytes=tight, max_slots=16, inner=inner, log=log, check_every=2,
+                                   pool=pool)
         serve["budget_2x_largest"] = {k: serve_tight[k] for k in
                                       ("requests", "arena_bytes", "p50_ms", "p99_ms", "solves_per_s",
                                        "max_in_flight", "max_queued")}
-        del fields
+        serve_fields_host = [(f[0], f[3]) for f in fields] if not args.no_oracle_check else None
+        del fields, pool
         torch.cuda.empty_cache()
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
@@ -507,6 +667,10 @@ def main():
                           f"iterations ({times[1]:.1f} s, {times[2]:.1f} s); one iteration = {t_iter:.2f} s; "
                           f"value = the step's algorithmic bytes per batch iteration / ({NRHS} x that time)")}
         log(f"cpu baseline {cpu}")
+        if not args.no_oracle_check:
+            cpu["oracle_check"] = oracle_checks(oracle, dims, U, x_host, x64_host, xtg_host, serve_kept,
+                                                serve_fields_host)
+            log(f"oracle check {cpu['oracle_check']}")
 
     per_rhs_mixed = ms_per_step * 1e-3 / NRHS
     out = {
@@ -542,6 +706,8 @@ def main():
                              "iters_mixed_max": max(iters), "reliable_updates_max": n_ru,
                              "iters_fp64": fp64["iters"] if fp64 else None,
                              "true_rel_resid_max": worst_res,
+                             "oracle_true_rel_resid_max": (cpu or {}).get("oracle_check", {}).get(
+                                 "step_max"),
                              "fp64_true_rel_resid": fp64["true_rel_resid"] if fp64 else None,
                              "mixed_single_rhs_s": (round(fp64["mixed_single_rhs"]["seconds"], 3)
                                                     if fp64 else None),
@@ -549,6 +715,7 @@ def main():
                                                     if fp64 else None),
                              "defect_correction": dc},
         "dslash_single_rhs": table,
+        "next1": next1,
         "dslash_rhs_scan": rhs_scan,
         "copy_GBps": round(copy_gbs, 1),
         "stream_GBps": stream_gbs,

@@ -16,7 +16,9 @@
  *     and the defect-correction scheme (Section 5.2, Algorithm 1).
  *
  * Conventions
- *   Lattice dims (Lx, Ly, Lz, Lt), all even, each >= 2.  Direction mu = 0..3
+ *   Lattice dims (Lx, Ly, Lz, Lt), all even, each >= 2, with Vh = V/2 at most
+ *   22,369,600 (one FP64 parity field of one right-hand side below 4 GiB, the
+ *   range of the kernels' buffer descriptors).  Direction mu = 0..3
  *   is x, y, z, t (the paper's mu = 1..4).  Site index
  *   lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2 (0 = even);
  *   checkerboard index cb = lex / 2 within a parity.  Periodic in x, y, z;
@@ -39,8 +41,8 @@
  *   The caller allocates every device buffer (for example as PyTorch tensors)
  *   and passes raw device pointers; the library never frees caller memory and
  *   never allocates device memory in the operator or solver paths.  `stream`
- *   is a hipStream_t (NULL = default stream).  Device pointers must be 16-byte
- *   aligned (256-byte alignment is recommended).
+ *   is a hipStream_t (NULL = default stream).  Device pointers must be
+ *   256-byte aligned.
  *
  * Errors
  *   Every entry point validates its arguments before launching anything and
@@ -171,8 +173,8 @@ wd_status wd_spinor_decode_full(const wd_lattice *lat, wd_prec prec, int32_t nrh
                                 double *canon_full, const void *field, void *stream);
 
 /* Spin bases of encoded fields (Appendix B).  Canonical arrays are always in
- * the DeGrand-Rossi basis; every encode, decode and operator entry point above
- * works on DeGrand-Rossi fields.  The UKQCD ("non-relativistic") basis is the
+ * the DeGrand-Rossi basis; every encode, decode and operator entry point
+ * works on DeGrand-Rossi fields unless it takes a basis argument.  The UKQCD ("non-relativistic") basis is the
  * rotation psi_UK = S psi_DR with S = [[0, 1, 0, 1], [-1, 0, -1, 0],
  * [0, 1, 0, -1], [-1, 0, 1, 0]] / sqrt(2), in which gamma_t is
  * diag(1, 1, -1, -1): a temporal hop then reads half a spinor.  The solvers
@@ -190,32 +192,54 @@ wd_status wd_spinor_decode_basis(const wd_lattice *lat, wd_prec prec, int32_t nr
 
 /* ---- operators ------------------------------------------------------------------ */
 
-/* Hopping term restricted to parities (Eq. 1): out_p = D_{p,1-p} in_{1-p}, or
- * its adjoint (dagger = 1: projectors 1 -+ gamma_mu swapped, links daggered).
- * out and in are encoded fields of precision prec (the gauge handle must hold
- * prec) with nrhs right-hand sides; out is parity out_parity, in the other
- * parity.  No factor kappa.  Asynchronous on stream. */
-wd_status wilson_dslash(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
-                        int32_t dagger, wd_prec prec, int32_t nrhs, void *stream);
+/* Operators on canonical FP64 parity spinors (device, [nrhs][Vh][4][3][2],
+ * DeGrand-Rossi basis, sites in cb order).  `prec` selects the storage and
+ * arithmetic of the application: the input is encoded into `prec` inside
+ * (16-bit formats: per-site norm, Section 4.6), the operator runs on the
+ * encoded fields and the result is decoded back to FP64, so for prec !=
+ * WD_FP64 the result carries that format's rounding.  The gauge handle must
+ * hold `prec`.  Scratch fields live in the caller's device workspace
+ * (>= wd_operator_workspace_bytes bytes, 256-byte aligned); out may alias in.
+ * Asynchronous on stream; WD_EINVAL before any launch on a bad argument. */
 
-/* wilson_dslash on fields in spin basis `basis` (WD_BASIS_*); the result is
- * S D S^T applied to in, i.e. the same operator written in that basis
- * (Appendix B).  WD_EINVAL for an unknown basis. */
-wd_status wilson_dslash_basis(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
-                              int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void *stream);
+/* Workspace bytes of wilson_dslash, wilson_mat_pc and mdagm for (lattice,
+ * prec, nrhs): four encoded parity fields.  0 on invalid arguments. */
+size_t wd_operator_workspace_bytes(const wd_lattice *lat, wd_prec prec, int32_t nrhs);
 
-/* Even-odd operator (Eq. 2): out_e = in_e - kappa^2 D_eo D_oe in_e (dagger = 1:
- * the adjoint M_hat^dagger).  tmp_odd is an odd-parity field of the same
- * precision and nrhs.  Asynchronous on stream. */
-wd_status wilson_mat_pc(const wd_gauge *g, double kappa, void *out, const void *in,
-                        void *tmp_odd, int32_t dagger, wd_prec prec, int32_t nrhs,
+/* Hopping term restricted to parities (Section 3, Eq. 1):
+ * out_p = D_{p,1-p} in_{1-p}, p = out_parity; with dagger = 1 its adjoint
+ * (projectors 1 -+ gamma_mu swapped, links daggered).  No factor kappa. */
+wd_status wilson_dslash(const wd_gauge *g, double *out, const double *in, int32_t out_parity,
+                        int32_t dagger, wd_prec prec, int32_t nrhs, void *workspace, size_t ws_bytes,
                         void *stream);
 
-/* Normal operator out_e = M_hat^dagger M_hat in_e.  tmp_odd (odd parity) and
- * tmp_even (even parity) are scratch fields of the same precision and nrhs.
- * Asynchronous on stream. */
-wd_status mdagm(const wd_gauge *g, double kappa, void *out, const void *in, void *tmp_odd,
-                void *tmp_even, wd_prec prec, int32_t nrhs, void *stream);
+/* Even-odd preconditioned operator (Section 3, Eq. 2) on even spinors:
+ * out_e = in_e - kappa^2 D_eo D_oe in_e; dagger = 1 gives M_hat^dagger. */
+wd_status wilson_mat_pc(const wd_gauge *g, double kappa, double *out, const double *in, int32_t dagger,
+                        wd_prec prec, int32_t nrhs, void *workspace, size_t ws_bytes, void *stream);
+
+/* Normal operator of the CG solver (Section 5.1): out_e = M_hat^dagger M_hat in_e. */
+wd_status mdagm(const wd_gauge *g, double kappa, double *out, const double *in, wd_prec prec,
+                int32_t nrhs, void *workspace, size_t ws_bytes, void *stream);
+
+/* Fast path: the same operators on encoded device fields (wd_spinor_encode*),
+ * with no conversion.  out and in are fields of precision prec with nrhs
+ * right-hand sides; they must not alias.  Asynchronous on stream.
+ *   wd_dslash_field:       out_p = D_{p,1-p} in (Eq. 1), or its adjoint.
+ *   wd_dslash_field_basis: the same on fields in spin basis `basis`
+ *                          (WD_BASIS_*): S D S^T applied to in (Appendix B).
+ *   wd_mat_pc_field:       out_e = in_e - kappa^2 D_eo D_oe in_e (Eq. 2) or its
+ *                          adjoint; tmp_odd is an odd field of (prec, nrhs).
+ *   wd_mdagm_field:        out_e = M_hat^dagger M_hat in_e (Section 5.1);
+ *                          tmp_odd, tmp_even are fields of (prec, nrhs). */
+wd_status wd_dslash_field(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
+                          int32_t dagger, wd_prec prec, int32_t nrhs, void *stream);
+wd_status wd_dslash_field_basis(const wd_gauge *g, void *out, const void *in, int32_t out_parity,
+                                int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void *stream);
+wd_status wd_mat_pc_field(const wd_gauge *g, double kappa, void *out, const void *in, void *tmp_odd,
+                          int32_t dagger, wd_prec prec, int32_t nrhs, void *stream);
+wd_status wd_mdagm_field(const wd_gauge *g, double kappa, void *out, const void *in, void *tmp_odd,
+                         void *tmp_even, wd_prec prec, int32_t nrhs, void *stream);
 
 /* ---- solvers ------------------------------------------------------------------- */
 
@@ -324,10 +348,14 @@ wd_status wd_server_create(void *arena, size_t arena_bytes, const wd_serve_param
 wd_status wd_server_submit(wd_server *s, int32_t solver, const wd_gauge *g, double kappa, double *x,
                            const double *b, const wd_solve_params *params, int64_t *request_id);
 
-/* One scheduling round: admit queued requests that fit, launch one round of
- * iterations on every in-flight solve (each on its own stream, so they
- * overlap on the device), then complete them; finished solves release their
- * slot and memory.  Reports the in-flight and queued counts. */
+/* One scheduling round (iters_per_pump times over): admit queued requests
+ * that fit, launch the next check_every iterations of every in-flight solve
+ * that has none outstanding (each on its own stream, so they overlap on the
+ * device), then wait until at least one in-flight solve's iterations have
+ * landed and complete every solve whose iterations have (its reliable
+ * updates run then); a solve is never held back by the others.  Finished
+ * solves release their slot and memory and queued requests move in.
+ * Reports the in-flight and queued counts. */
 wd_status wd_server_pump(wd_server *s, int32_t *n_active, int32_t *n_queued);
 
 /* Result of a request: *done = 1 once finished (info[0..nrhs) filled, status

@@ -17,7 +17,8 @@ __all__ = [
     "Lattice", "WDError", "Gauge", "PREC", "WD_FP64", "WD_FP32", "WD_HALF_I16", "WD_HALF_F16",
     "lattice", "prec_of", "wd_gauge_bytes", "wd_spinor_bytes", "new_field", "wd_spinor_encode",
     "wd_spinor_decode", "wd_spinor_encode_full", "wd_spinor_decode_full", "wilson_dslash",
-    "wd_spinor_encode_basis", "wd_spinor_decode_basis", "wilson_dslash_basis",
+    "wd_spinor_encode_basis", "wd_spinor_decode_basis", "wd_dslash_field", "wd_dslash_field_basis",
+    "wd_mat_pc_field", "wd_mdagm_field", "wd_operator_workspace_bytes", "new_operator_workspace",
     "WD_BASIS_DEGRAND_ROSSI", "WD_BASIS_UKQCD",
     "wilson_mat_pc", "mdagm", "gauge_fix_temporal", "wd_gauge_rotate_spinor", "WD_GAUGE_TEMPORAL",
 ]
@@ -135,27 +136,58 @@ def wd_spinor_decode_full(lat, prec, nrhs, parity, canon_full, field, stream=Non
                  "wd_spinor_decode_full")
 
 
-def wilson_dslash(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1,
+def wd_operator_workspace_bytes(lat: Lattice, prec, nrhs: int = 1) -> int:
+    return int(lib().wd_operator_workspace_bytes(ctypes.byref(lat), prec_of(prec), nrhs))
+
+
+def new_operator_workspace(lat: Lattice, prec, nrhs: int = 1, device="cuda"):
+    """Device workspace of wilson_dslash / wilson_mat_pc / mdagm."""
+    import torch
+    n = wd_operator_workspace_bytes(lat, prec, nrhs)
+    if n == 0:
+        raise WDError(-1, "new_operator_workspace", "invalid lattice, precision or nrhs")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def wilson_dslash(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int, workspace,
                   stream=None):
-    return check(lib().wilson_dslash(gauge.handle, ptr(out), ptr(inp), out_parity, dagger, prec_of(prec),
-                                     nrhs, stream_ptr(stream)), "wilson_dslash")
+    """out, inp: canonical FP64 parity spinors (device tensors)."""
+    return check(lib().wilson_dslash(gauge.handle, ptr(out), ptr(inp), out_parity, dagger, prec_of(prec), nrhs,
+                                     ptr(workspace), workspace.numel(), stream_ptr(stream)), "wilson_dslash")
 
 
-def wilson_dslash_basis(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1,
-                        basis: int = 1, stream=None):
-    return check(lib().wilson_dslash_basis(gauge.handle, ptr(out), ptr(inp), out_parity, dagger,
-                                           prec_of(prec), nrhs, basis, stream_ptr(stream)), "wilson_dslash_basis")
+def wilson_mat_pc(gauge: Gauge, kappa: float, out, inp, dagger: int, prec, nrhs: int, workspace, stream=None):
+    return check(lib().wilson_mat_pc(gauge.handle, kappa, ptr(out), ptr(inp), dagger, prec_of(prec), nrhs,
+                                     ptr(workspace), workspace.numel(), stream_ptr(stream)), "wilson_mat_pc")
 
 
-def wilson_mat_pc(gauge: Gauge, kappa: float, out, inp, tmp_odd, dagger: int, prec, nrhs: int = 1,
-                  stream=None):
-    return check(lib().wilson_mat_pc(gauge.handle, kappa, ptr(out), ptr(inp), ptr(tmp_odd), dagger,
-                                     prec_of(prec), nrhs, stream_ptr(stream)), "wilson_mat_pc")
+def mdagm(gauge: Gauge, kappa: float, out, inp, prec, nrhs: int, workspace, stream=None):
+    return check(lib().mdagm(gauge.handle, kappa, ptr(out), ptr(inp), prec_of(prec), nrhs, ptr(workspace),
+                             workspace.numel(), stream_ptr(stream)), "mdagm")
 
 
-def mdagm(gauge: Gauge, kappa: float, out, inp, tmp_odd, tmp_even, prec, nrhs: int = 1, stream=None):
-    return check(lib().mdagm(gauge.handle, kappa, ptr(out), ptr(inp), ptr(tmp_odd), ptr(tmp_even),
-                             prec_of(prec), nrhs, stream_ptr(stream)), "mdagm")
+def wd_dslash_field(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1, stream=None):
+    """Fast path on encoded fields (see wd_spinor_encode*)."""
+    return check(lib().wd_dslash_field(gauge.handle, ptr(out), ptr(inp), out_parity, dagger, prec_of(prec),
+                                       nrhs, stream_ptr(stream)), "wd_dslash_field")
+
+
+def wd_dslash_field_basis(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1,
+                          basis: int = 1, stream=None):
+    return check(lib().wd_dslash_field_basis(gauge.handle, ptr(out), ptr(inp), out_parity, dagger,
+                                             prec_of(prec), nrhs, basis, stream_ptr(stream)),
+                 "wd_dslash_field_basis")
+
+
+def wd_mat_pc_field(gauge: Gauge, kappa: float, out, inp, tmp_odd, dagger: int, prec, nrhs: int = 1,
+                    stream=None):
+    return check(lib().wd_mat_pc_field(gauge.handle, kappa, ptr(out), ptr(inp), ptr(tmp_odd), dagger,
+                                       prec_of(prec), nrhs, stream_ptr(stream)), "wd_mat_pc_field")
+
+
+def wd_mdagm_field(gauge: Gauge, kappa: float, out, inp, tmp_odd, tmp_even, prec, nrhs: int = 1, stream=None):
+    return check(lib().wd_mdagm_field(gauge.handle, kappa, ptr(out), ptr(inp), ptr(tmp_odd), ptr(tmp_even),
+                                      prec_of(prec), nrhs, stream_ptr(stream)), "wd_mdagm_field")
 
 
 # ---- solvers ------------------------------------------------------------------------

@@ -79,14 +79,22 @@ def lib():
         for name in ("wd_spinor_encode_basis", "wd_spinor_decode_basis"):
             getattr(L, name).argtypes = [lp, i32, i32, i32, vp, vp, vp]
             getattr(L, name).restype = i32
-        L.wilson_dslash.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
+        L.wd_operator_workspace_bytes.argtypes = [lp, i32, i32]
+        L.wd_operator_workspace_bytes.restype = sz
+        L.wilson_dslash.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, sz, vp]
         L.wilson_dslash.restype = i32
-        L.wilson_dslash_basis.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp]
-        L.wilson_dslash_basis.restype = i32
-        L.wilson_mat_pc.argtypes = [vp, dbl, vp, vp, vp, i32, i32, i32, vp]
+        L.wilson_mat_pc.argtypes = [vp, dbl, vp, vp, i32, i32, i32, vp, sz, vp]
         L.wilson_mat_pc.restype = i32
-        L.mdagm.argtypes = [vp, dbl, vp, vp, vp, vp, i32, i32, vp]
+        L.mdagm.argtypes = [vp, dbl, vp, vp, i32, i32, vp, sz, vp]
         L.mdagm.restype = i32
+        L.wd_dslash_field.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
+        L.wd_dslash_field.restype = i32
+        L.wd_dslash_field_basis.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp]
+        L.wd_dslash_field_basis.restype = i32
+        L.wd_mat_pc_field.argtypes = [vp, dbl, vp, vp, vp, i32, i32, i32, vp]
+        L.wd_mat_pc_field.restype = i32
+        L.wd_mdagm_field.argtypes = [vp, dbl, vp, vp, vp, vp, i32, i32, vp]
+        L.wd_mdagm_field.restype = i32
         _declare_solver(L)
         _lib = L
     return _lib

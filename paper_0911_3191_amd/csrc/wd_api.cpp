@@ -46,6 +46,10 @@ size_t spinor_field_bytes(const Geom& g, wd_prec p, int nrhs) {
   return b;
 }
 
+// Largest Vh whose FP64 parity field (stride * 192 bytes, stride a multiple of
+// 64 sites) fits a 32-bit buffer descriptor.
+static constexpr int64_t kMaxVh = ((int64_t)UINT32_MAX / 192) / 64 * 64;
+
 static bool prec_ok(wd_prec p) { return p >= WD_FP64 && p <= WD_HALF_F16; }
 
 // Lattice check: dims even, >= 2, volume within int32 checkerboard indexing.
@@ -59,7 +63,13 @@ static wd_status check_lattice(const wd_lattice* lat) {
                                  " = " + std::to_string(L) + ")");
     V *= L;
   }
-  if (V / 2 > (int64_t)1 << 30) return fail(WD_EINVAL, "lattice volume too large (Vh > 2^30)");
+  // The kernels address one right-hand side of a field, and one (parity, mu)
+  // block of links, through a buffer descriptor whose size is 32-bit: the
+  // largest such range, an FP64 spinor (12 chunks of 16 bytes per site), must
+  // stay below 4 GiB.  A larger lattice would make loads read zeros.
+  if (field_stride(V / 2) * 192 > (int64_t)UINT32_MAX)
+    return fail(WD_EINVAL, "lattice too large: Vh = " + std::to_string(V / 2) + " > " +
+                               std::to_string(kMaxVh) + " (one FP64 parity field must stay below 4 GiB)");
   if (lat->t_antiperiodic != 0 && lat->t_antiperiodic != 1)
     return fail(WD_EINVAL, "t_antiperiodic must be 0 or 1");
   return WD_OK;
@@ -67,8 +77,8 @@ static wd_status check_lattice(const wd_lattice* lat) {
 
 static wd_status check_ptr(const void* p, const char* what) {
   if (!p) return fail(WD_EINVAL, std::string(what) + " is NULL");
-  if (reinterpret_cast<uintptr_t>(p) % 16)
-    return fail(WD_EINVAL, std::string(what) + " is not 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(p) % 256)
+    return fail(WD_EINVAL, std::string(what) + " is not 256-byte aligned");
   return WD_OK;
 }
 
@@ -290,8 +300,8 @@ wd_status wd_spinor_decode_full(const wd_lattice* lat, wd_prec prec, int32_t nrh
                     "spinor decode (full lattice)");
 }
 
-wd_status wilson_dslash_basis(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
-                              int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void* stream) {
+wd_status wd_dslash_field_basis(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
+                                int32_t dagger, wd_prec prec, int32_t nrhs, int32_t basis, void* stream) {
   g_last_error.clear();
   wd_status st = check_gauge(g, prec);
   if (st) return st;
@@ -303,16 +313,16 @@ wd_status wilson_dslash_basis(const wd_gauge* g, void* out, const void* in, int3
   const Geom& geo = g->geom;
   return hip_status(launch_dslash(g, prec, field_of(geo, out, nrhs), field_of(geo, const_cast<void*>(in), nrhs),
                                   out_parity, dagger, nullptr, 0.0, static_cast<hipStream_t>(stream), basis),
-                    "wilson_dslash");
+                    "wd_dslash_field");
 }
 
-wd_status wilson_dslash(const wd_gauge* g, void* out, const void* in, int32_t out_parity,
-                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
-  return wilson_dslash_basis(g, out, in, out_parity, dagger, prec, nrhs, WD_BASIS_DEGRAND_ROSSI, stream);
+wd_status wd_dslash_field(const wd_gauge* g, void* out, const void* in, int32_t out_parity, int32_t dagger,
+                          wd_prec prec, int32_t nrhs, void* stream) {
+  return wd_dslash_field_basis(g, out, in, out_parity, dagger, prec, nrhs, WD_BASIS_DEGRAND_ROSSI, stream);
 }
 
-wd_status wilson_mat_pc(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
-                        int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
+wd_status wd_mat_pc_field(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
+                          int32_t dagger, wd_prec prec, int32_t nrhs, void* stream) {
   g_last_error.clear();
   wd_status st = check_gauge(g, prec);
   if (st) return st;
@@ -328,20 +338,123 @@ wd_status wilson_mat_pc(const wd_gauge* g, double kappa, void* out, const void* 
   Field ft = field_of(geo, tmp_odd, nrhs);
   hipError_t e = launch_dslash(g, prec, ft, fi, 1, dagger, nullptr, 0.0, s);
   if (e == hipSuccess) e = launch_dslash(g, prec, fo, ft, 0, dagger, &fi, -kappa * kappa, s);
-  return hip_status(e, "wilson_mat_pc");
+  return hip_status(e, "wd_mat_pc_field");
 }
 
-wd_status mdagm(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
-                void* tmp_even, wd_prec prec, int32_t nrhs, void* stream) {
+wd_status wd_mdagm_field(const wd_gauge* g, double kappa, void* out, const void* in, void* tmp_odd,
+                         void* tmp_even, wd_prec prec, int32_t nrhs, void* stream) {
   g_last_error.clear();
   wd_status st = check_gauge(g, prec);
   if (st) return st;
   if ((st = check_ptr(tmp_even, "tmp_even"))) return st;
   if (tmp_even == in || tmp_even == out || tmp_even == tmp_odd)
     return fail(WD_EINVAL, "fields must not alias");
-  st = wilson_mat_pc(g, kappa, tmp_even, in, tmp_odd, 0, prec, nrhs, stream);
+  st = wd_mat_pc_field(g, kappa, tmp_even, in, tmp_odd, 0, prec, nrhs, stream);
   if (st) return st;
-  return wilson_mat_pc(g, kappa, out, tmp_even, tmp_odd, 1, prec, nrhs, stream);
+  return wd_mat_pc_field(g, kappa, out, tmp_even, tmp_odd, 1, prec, nrhs, stream);
+}
+
+// ---- operators on canonical FP64 parity spinors -------------------------------------
+// The workspace holds four encoded parity fields of (prec, nrhs), each
+// starting on a 256-byte boundary: the encoded input, the result and one odd
+// and one even temporary.
+
+size_t wd_operator_workspace_bytes(const wd_lattice* lat, wd_prec prec, int32_t nrhs) {
+  if (check_lattice(lat) != WD_OK || !prec_ok(prec) || check_nrhs(nrhs) != WD_OK) return 0;
+  return 4 * operator_field_slot(make_geom(*lat), prec, nrhs);
+}
+
+}  // extern "C"
+
+namespace wd {
+
+size_t operator_field_slot(const Geom& g, wd_prec prec, int nrhs) {
+  return (spinor_field_bytes(g, prec, nrhs) + 255) / 256 * 256;
+}
+
+// Argument checks shared by the canonical operator entry points.
+static wd_status check_canon_op(const wd_gauge* g, void* out, const void* in, wd_prec prec, int nrhs,
+                                const void* ws, size_t ws_bytes, size_t* slot) {
+  wd_status st = check_gauge(g, prec);
+  if (st) return st;
+  if ((st = check_nrhs(nrhs)) || (st = check_ptr(out, "out")) || (st = check_ptr(in, "in")) ||
+      (st = check_ptr(ws, "workspace")))
+    return st;
+  *slot = operator_field_slot(g->geom, prec, nrhs);
+  if (ws_bytes < 4 * *slot)
+    return fail(WD_EINVAL, "workspace too small: " + std::to_string(ws_bytes) + " < " +
+                               std::to_string(4 * *slot) + " (wd_operator_workspace_bytes)");
+  return WD_OK;
+}
+
+// The canonical operators: encode `in`, apply the operator on encoded
+// fields, decode into `out` (all on `s`).  op: 0 dslash, 1 M_hat (dagger
+// selects the adjoint), 2 M_hat^dagger M_hat.  out may alias in: the input
+// is encoded before anything is written to out.
+hipError_t canon_operator(const wd_gauge* g, int op, double kappa, double* out, const double* in,
+                          int out_parity, int dagger, wd_prec prec, int nrhs, char* ws, size_t slot,
+                          hipStream_t s) {
+  const Geom& geo = g->geom;
+  Field fin = field_of(geo, ws, nrhs), fout = field_of(geo, ws + slot, nrhs);
+  Field fodd = field_of(geo, ws + 2 * slot, nrhs), feven = field_of(geo, ws + 3 * slot, nrhs);
+  hipError_t e = launch_spinor_encode(geo, prec, fin, in, s);
+  if (e != hipSuccess) return e;
+  if (op == 0) {
+    e = launch_dslash(g, prec, fout, fin, out_parity, dagger, nullptr, 0.0, s);
+  } else {
+    const double a = -kappa * kappa;
+    e = launch_dslash(g, prec, fodd, fin, 1, op == 1 ? dagger : 0, nullptr, 0.0, s);
+    if (e == hipSuccess)
+      e = launch_dslash(g, prec, op == 1 ? fout : feven, fodd, 0, op == 1 ? dagger : 0, &fin, a, s);
+    if (op == 2) {
+      if (e == hipSuccess) e = launch_dslash(g, prec, fodd, feven, 1, 1, nullptr, 0.0, s);
+      if (e == hipSuccess) e = launch_dslash(g, prec, fout, fodd, 0, 1, &feven, a, s);
+    }
+  }
+  if (e != hipSuccess) return e;
+  return launch_spinor_decode(geo, prec, out, fout, s);
+}
+
+}  // namespace wd
+
+extern "C" {
+
+wd_status wilson_dslash(const wd_gauge* g, double* out, const double* in, int32_t out_parity, int32_t dagger,
+                        wd_prec prec, int32_t nrhs, void* workspace, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  size_t slot = 0;
+  wd_status st = check_canon_op(g, out, in, prec, nrhs, workspace, ws_bytes, &slot);
+  if (st) return st;
+  if (out_parity != 0 && out_parity != 1) return fail(WD_EINVAL, "out_parity must be 0 or 1");
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  return hip_status(canon_operator(g, 0, 0.0, out, in, out_parity, dagger, prec, nrhs,
+                                   static_cast<char*>(workspace), slot, static_cast<hipStream_t>(stream)),
+                    "wilson_dslash");
+}
+
+wd_status wilson_mat_pc(const wd_gauge* g, double kappa, double* out, const double* in, int32_t dagger,
+                        wd_prec prec, int32_t nrhs, void* workspace, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  size_t slot = 0;
+  wd_status st = check_canon_op(g, out, in, prec, nrhs, workspace, ws_bytes, &slot);
+  if (st) return st;
+  if (!std::isfinite(kappa) || kappa <= 0) return fail(WD_EINVAL, "kappa must be finite and > 0");
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  return hip_status(canon_operator(g, 1, kappa, out, in, 0, dagger, prec, nrhs, static_cast<char*>(workspace),
+                                   slot, static_cast<hipStream_t>(stream)),
+                    "wilson_mat_pc");
+}
+
+wd_status mdagm(const wd_gauge* g, double kappa, double* out, const double* in, wd_prec prec, int32_t nrhs,
+                void* workspace, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  size_t slot = 0;
+  wd_status st = check_canon_op(g, out, in, prec, nrhs, workspace, ws_bytes, &slot);
+  if (st) return st;
+  if (!std::isfinite(kappa) || kappa <= 0) return fail(WD_EINVAL, "kappa must be finite and > 0");
+  return hip_status(canon_operator(g, 2, kappa, out, in, 0, 0, prec, nrhs, static_cast<char*>(workspace), slot,
+                                   static_cast<hipStream_t>(stream)),
+                    "mdagm");
 }
 
 }  // extern "C"

@@ -44,6 +44,9 @@ struct Field {
 };
 
 size_t spinor_field_bytes(const Geom& g, wd_prec p, int nrhs);
+// Bytes of one field of the canonical operators' workspace (rounded up to
+// 256 so every field starts aligned); the workspace holds four.
+size_t operator_field_slot(const Geom& g, wd_prec prec, int nrhs);
 
 }  // namespace wd
 
@@ -210,6 +213,14 @@ hipError_t solver_init_flags(int nrhs, int* fl, int* active, int* rumask, hipStr
 bool solver_finished(wd_solver* h);
 hipError_t solver_issue(wd_solver* h);   // launch one iteration, returns at once
 wd_status solver_complete(wd_solver* h); // wait for it, reliable update if triggered
+
+// Canonical FP64 parity spinors in, encoded fields of `prec` in the
+// workspace `ws` (four fields of `slot` bytes), canonical out: op 0 is the
+// hopping term D_{p,1-p}, op 1 M_hat (adjoint with dagger), op 2
+// M_hat^dagger M_hat.  Asynchronous on s.
+hipError_t canon_operator(const wd_gauge* g, int op, double kappa, double* out, const double* in,
+                          int out_parity, int dagger, wd_prec prec, int nrhs, char* ws, size_t slot,
+                          hipStream_t s);
 
 // ---- error reporting ------------------------------------------------------------
 void set_error(const std::string& msg);

@@ -15,7 +15,10 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxDot = 4;  // components per partial record
 
 // Sum v[0..N) over the block; thread 0 writes out[0..N).  Every thread of
-// the block must call it (inactive sites contribute zeros).
+// the block must call it (inactive sites contribute zeros).  The LDS slots
+// are shared by every call with the same N in a kernel, so the trailing
+// barrier keeps a following call (the next right-hand side of a multi-RHS
+// launch) from overwriting them before thread 0 has read this call's sums.
 template <int N>
 __device__ __forceinline__ void block_sum_store(double (&v)[N], double* out) {
 #pragma unroll
@@ -38,10 +41,12 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double* out) {
       out[k] = t;
     }
   }
+  __syncthreads();
 }
 
 // Fixed-order sum of nb partial records (stride kMaxDot) into res[0..N).
-// Called by all threads of one block; the result is valid in thread 0.
+// Called by all threads of one block; the result is valid in thread 0.  Ends
+// with a barrier so that a second call may reuse the LDS slots at once.
 template <int N>
 __device__ __forceinline__ void sum_partials(const double* part, int nb, double (&res)[N]) {
 #pragma unroll
@@ -61,6 +66,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nb, double 
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) res[k] = sm[k][0];
+  __syncthreads();
 }
 
 }  // namespace wd

@@ -2,12 +2,15 @@
 //
 // Requests queue in FIFO order; a request is admitted when a slot (one HIP
 // stream) and enough of the caller's device arena for its solver workspace
-// are free.  Every scheduling round launches one iteration on each in-flight
-// solve, each on its own stream, before waiting on any of them, so the solves
-// run concurrently on the device; finished solves give back their slot and
-// arena memory and the next queued requests move in.  The per-RHS arithmetic
-// of a solve does not depend on what else runs, so a result is the same alone
-// and in the mix.  Calls on one server must not overlap (single host thread).
+// are free.  Each in-flight solve advances on its own stream: the scheduler
+// launches its next batch of iterations (and the copy of its flags) as soon
+// as the previous one has landed, which it learns from an event recorded
+// after the flag copy, so a solve on a small lattice never waits for the
+// iterations of a large one.  Finished solves give back their slot and arena
+// memory and the next queued requests move in at once.  The per-RHS
+// arithmetic of a solve does not depend on what else runs, so a result is
+// the same alone and in the mix.  Calls on one server must not overlap
+// (single host thread).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +18,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "wd_internal.h"
@@ -71,6 +75,7 @@ struct Request {
   size_t off = 0;
   int slot = -1;
   wd_solver* h = nullptr;
+  bool issued = false;  // iterations launched whose flags have not been read yet
   wd_status status = WD_OK;
   std::vector<wd_solve_info> info;
 };
@@ -83,6 +88,7 @@ struct wd_server {
   Arena arena;
   wd_serve_params prm;
   std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;  // per slot: recorded after the issued work's flag copy
   std::vector<int64_t> slot_req;  // request in each slot, -1 if free
   std::deque<int64_t> queue;
   std::map<int64_t, Request> reqs;
@@ -147,13 +153,19 @@ wd_status wd_server_create(void* arena, size_t arena_bytes, const wd_serve_param
   if (!s) return fail(WD_ENOMEM, "host allocation failed");
   for (int i = 0; i < params->max_slots; ++i) {
     hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      s->streams.push_back(st);
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) s->events.push_back(ev);
+    }
     if (e != hipSuccess) {
       for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+      for (hipEvent_t t : s->events) (void)hipEventDestroy(t);
       delete s;
       return fail(WD_EDEVICE, std::string("stream creation: ") + hipGetErrorString(e));
     }
-    s->streams.push_back(st);
   }
   s->slot_req.assign(params->max_slots, -1);
   *out = s;
@@ -187,27 +199,50 @@ wd_status wd_server_pump(wd_server* s, int32_t* n_active, int32_t* n_queued) {
   set_error("");
   if (!s) return fail(WD_EINVAL, "server is NULL");
   admit(s);
+  // Each round: launch the next iterations of every in-flight solve that has
+  // none outstanding, then complete whichever solves have landed (at least
+  // one; the host polls the slots' events meanwhile), releasing finished
+  // ones and admitting queued requests into their slots.
   for (int round = 0; round < s->prm.iters_per_pump; ++round) {
-    std::vector<Request*> live;
-    for (int64_t id : s->slot_req)
-      if (id >= 0) live.push_back(&s->reqs.at(id));
-    // launch one iteration everywhere first, then wait: the solves overlap
-    std::vector<Request*> issued;
-    for (Request* r : live) {
-      if (solver_finished(r->h)) continue;
-      hipError_t e = solver_issue(r->h);
-      if (e != hipSuccess) return fail(WD_EDEVICE, std::string("serve issue: ") + hipGetErrorString(e));
-      issued.push_back(r);
+    bool outstanding = false;
+    for (size_t slot = 0; slot < s->slot_req.size(); ++slot) {
+      if (s->slot_req[slot] < 0) continue;
+      Request& r = s->reqs.at(s->slot_req[slot]);
+      if (!r.issued && solver_finished(r.h)) {  // e.g. converged at prepare: release at once
+        finish(s, r);
+        continue;
+      }
+      if (!r.issued) {
+        hipError_t e = solver_issue(r.h);
+        if (e == hipSuccess) e = hipEventRecord(s->events[slot], s->streams[slot]);
+        if (e != hipSuccess) return fail(WD_EDEVICE, std::string("serve issue: ") + hipGetErrorString(e));
+        r.issued = true;
+      }
+      outstanding |= r.issued;
     }
-    for (Request* r : issued) {
-      const wd_status st = solver_complete(r->h);
-      if (st < 0 && st != WD_EBREAKDOWN) return st;
+    if (!outstanding) {  // nothing in flight: admit what the released slots allow
+      admit(s);
+      break;
     }
-    for (Request* r : live)
-      if (solver_finished(r->h)) finish(s, *r);
-    if (issued.empty()) break;
+    int completed = 0;
+    while (completed == 0) {
+      for (size_t slot = 0; slot < s->slot_req.size(); ++slot) {
+        if (s->slot_req[slot] < 0) continue;
+        Request& r = s->reqs.at(s->slot_req[slot]);
+        if (!r.issued) continue;
+        const hipError_t q = hipEventQuery(s->events[slot]);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(WD_EDEVICE, std::string("serve wait: ") + hipGetErrorString(q));
+        r.issued = false;
+        ++completed;
+        const wd_status st = solver_complete(r.h);
+        if (st < 0 && st != WD_EBREAKDOWN) return st;
+        if (solver_finished(r.h)) finish(s, r);
+      }
+      if (completed == 0) std::this_thread::yield();
+    }
+    admit(s);
   }
-  admit(s);
   int na = 0;
   for (int64_t id : s->slot_req) na += id >= 0;
   if (n_active) *n_active = na;
@@ -244,6 +279,7 @@ wd_status wd_server_destroy(wd_server* s) {
   for (auto& kv : s->reqs)
     if (kv.second.h) wd_solver_end(kv.second.h, nullptr);
   for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+  for (hipEvent_t t : s->events) (void)hipEventDestroy(t);
   delete s;
   return WD_OK;
 }

@@ -85,7 +85,7 @@ def test_ukqcd_dslash_matches_oracle(setup, prec, dagger):
         src = po if p == 0 else pe
         fin = s.encode_parity(prec, src, basis=UK)
         fout = s.field(prec)
-        wd.wilson_dslash_basis(s.gauge, fout, fin, p, dagger, prec, 1, UK)
+        wd.wd_dslash_field_basis(s.gauge, fout, fin, p, dagger, prec, 1, UK)
         got = s.decode(prec, fout, basis=UK)
         ref = oracle.dslash_parity(s.dims, s.U, src, p, dagger=bool(dagger))
         err = rel_l2(got, ref)
@@ -105,7 +105,7 @@ def test_ukqcd_dslash_compressed_links(prec, recon, temporal):
     for dagger in (0, 1):
         fin = s.encode_parity(prec, po, basis=UK)
         fout = s.field(prec)
-        wd.wilson_dslash_basis(s.gauge, fout, fin, 0, dagger, prec, 1, UK)
+        wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, dagger, prec, 1, UK)
         ref = oracle.dslash_parity(dims, U, po, 0, dagger=bool(dagger))
         assert rel_l2(s.decode(prec, fout, basis=UK), ref) <= TOL[prec]
 
@@ -119,7 +119,7 @@ def test_ukqcd_periodic_t(prec):
     pe, _ = oracle.split(dims, psi)
     fin = s.encode_parity(prec, pe, basis=UK)
     fout = s.field(prec)
-    wd.wilson_dslash_basis(s.gauge, fout, fin, 1, 0, prec, 1, UK)
+    wd.wd_dslash_field_basis(s.gauge, fout, fin, 1, 0, prec, 1, UK)
     ref = oracle.dslash_parity(dims, U, pe, 1, antiperiodic_t=False)
     assert rel_l2(s.decode(prec, fout, basis=UK), ref) <= TOL[prec]
 
@@ -140,7 +140,7 @@ def test_ukqcd_every_launch_shape_and_rhs_count(prec, dims, monkeypatch):
             for lds in ((0, 1) if prec in ("i16", "f16") else (0,)):
                 monkeypatch.setenv("WD_DSLASH_SHAPE", f"{nr},0,{nsub},0,0,0,{lds}")
                 fout = s.field(prec, 5)
-                wd.wilson_dslash_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
+                wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
                 results[(nr, nsub, lds)] = s.decode(prec, fout, 5)
     ref = results[(2, 1, 0)]
     for key, val in results.items():
@@ -149,7 +149,7 @@ def test_ukqcd_every_launch_shape_and_rhs_count(prec, dims, monkeypatch):
     for k in range(5):
         f1 = s.encode_parity(prec, po[k], basis=UK)
         o1 = s.field(prec)
-        wd.wilson_dslash_basis(s.gauge, o1, f1, 0, 1, prec, 1, UK)
+        wd.wd_dslash_field_basis(s.gauge, o1, f1, 0, 1, prec, 1, UK)
         assert np.array_equal(s.decode(prec, o1), s.decode(prec, fout, 5)[k])
         expect = oracle.dslash_parity(dims, U, po[k], 0, dagger=True)
         assert rel_l2(from_uk(ref[k]), expect) <= TOL[prec]
@@ -174,7 +174,7 @@ def test_ukqcd_16bit_dslash_on_quantised_inputs(kind, dagger):
     po_q = from_uk(oracle.decode_spinor16(kind, q, nm))
     fin = s.encode_parity(kind, po, basis=UK)
     fout = s.field(kind)
-    wd.wilson_dslash_basis(s.gauge, fout, fin, 0, dagger, kind, 1, UK)
+    wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, dagger, kind, 1, UK)
     got = s.decode(kind, fout).reshape(s.Vh, 24)  # UKQCD components as stored
     ref = to_uk(oracle.dslash_parity(dims, Uq, po_q, 0, dagger=bool(dagger))).reshape(s.Vh, 24)
     site_norm = np.abs(ref).max(axis=1, keepdims=True)
@@ -191,5 +191,5 @@ def test_unknown_basis_is_rejected():
     s = Setup(dims, wdinputs.gauge_unit(dims), precs=("fp32",))
     f, g = s.field("fp32"), s.field("fp32")
     with pytest.raises(wd.WDError) as e:
-        wd.wilson_dslash_basis(s.gauge, f, g, 0, 0, "fp32", 1, 2)
+        wd.wd_dslash_field_basis(s.gauge, f, g, 0, 0, "fp32", 1, 2)
     assert e.value.status == wd.WD_EINVAL

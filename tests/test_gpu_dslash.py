@@ -40,7 +40,7 @@ def test_dslash_matches_oracle(setup, prec, dagger):
     for p in (0, 1):
         fin = s.encode_full(prec, psi, 1 - p)
         fout = s.field(prec)
-        wd.wilson_dslash(s.gauge, fout, fin, p, dagger, prec)
+        wd.wd_dslash_field(s.gauge, fout, fin, p, dagger, prec)
         got = s.decode(prec, fout)
         ref = oracle.dslash_parity(s.dims, s.U, po if p == 0 else pe, p, dagger=bool(dagger))
         err = rel_l2(got, ref)
@@ -56,7 +56,7 @@ def test_periodic_t(prec):
     _, po = oracle.split(dims, psi)
     fin = s.encode_full(prec, psi, 1)
     fout = s.field(prec)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, prec)
     ref = oracle.dslash_parity(dims, U, po, 0, antiperiodic_t=False)
     assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec]
 
@@ -70,12 +70,12 @@ def test_mat_pc_and_mdagm(setup, prec, dagger):
     pe, _ = oracle.split(s.dims, psi)
     fin = s.encode_parity(prec, pe)
     fout, tmp = s.field(prec), s.field(prec)
-    wd.wilson_mat_pc(s.gauge, kappa, fout, fin, tmp, dagger, prec)
+    wd.wd_mat_pc_field(s.gauge, kappa, fout, fin, tmp, dagger, prec)
     ref = oracle.mhat(s.dims, s.U, kappa, pe, dagger=bool(dagger))
     assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec]
     if dagger == 0:
         tmpe = s.field(prec)
-        wd.mdagm(s.gauge, kappa, fout, fin, tmp, tmpe, prec)
+        wd.wd_mdagm_field(s.gauge, kappa, fout, fin, tmp, tmpe, prec)
         ref2 = oracle.mhat(s.dims, s.U, kappa, oracle.mhat(s.dims, s.U, kappa, pe), dagger=True)
         assert rel_l2(s.decode(prec, fout), ref2) <= 2 * TOL[prec]
 
@@ -88,12 +88,12 @@ def test_multi_rhs_equals_single_rhs_bitwise(prec):
     srcs = wdinputs.spinor_gaussian(dims, 32, nrhs=3)
     fin = s.encode_full(prec, srcs, 1, nrhs=3)
     fout = s.field(prec, 3)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 3)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, prec, 3)
     batch = s.decode(prec, fout, 3)
     for k in range(3):
         f1 = s.encode_full(prec, srcs[k], 1)
         o1 = s.field(prec)
-        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        wd.wd_dslash_field(s.gauge, o1, f1, 0, 0, prec)
         assert np.array_equal(s.decode(prec, o1), batch[k])
 
 
@@ -114,7 +114,7 @@ def test_every_launch_shape_gives_identical_results(prec, dims, monkeypatch):
                 for lds in ((0, 1) if prec in ("i16", "f16") else (0,)):
                     monkeypatch.setenv("WD_DSLASH_SHAPE", f"{nr},{gslow},{nsub},0,0,0,{lds}")
                     fout = s.field(prec, 3)
-                    wd.wilson_dslash(s.gauge, fout, fin, 0, 1, prec, 3)
+                    wd.wd_dslash_field(s.gauge, fout, fin, 0, 1, prec, 3)
                     results[(nr, gslow, nsub, lds)] = s.decode(prec, fout, 3)
     ref = results[(1, 0, 1, 0)]
     for key, val in results.items():
@@ -153,7 +153,7 @@ def check_on_quantised_inputs(kind, dims, U, seed):
     po_q = oracle.decode_spinor16(kind, q, nm)
     fin = s.encode_parity(kind, po)
     fout = s.field(kind)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, kind)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, kind)
     got = s.decode(kind, fout).reshape(s.Vh, 24)
     ref = oracle.dslash_parity(dims, Uq, po_q, 0).reshape(s.Vh, 24)
     site_norm = np.abs(ref).max(axis=1, keepdims=True)
@@ -200,7 +200,7 @@ def test_accuracy_cdf_uniform_vector():
     for prec in ("fp64", "fp32"):
         fin = s.encode_parity(prec, ee)
         fout, tmp = s.field(prec), s.field(prec)
-        wd.wilson_mat_pc(s.gauge, 0.12, fout, fin, tmp, 0, prec)
+        wd.wd_mat_pc_field(s.gauge, 0.12, fout, fin, tmp, 0, prec)
         dev = np.abs(s.decode(prec, fout) - ref).max() / (scale * ulp[prec])
         assert dev < 200, f"{prec}: first deviation at {dev:.1f} ulp"
 
@@ -214,10 +214,10 @@ def test_sixty_four_rhs_in_one_launch_equal_single_rhs(prec):
     srcs = wdinputs.spinor_gaussian(dims, 72, nrhs=64)
     fin = s.encode_full(prec, srcs, 1, nrhs=64)
     fout = s.field(prec, 64)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 64)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, prec, 64)
     multi = s.decode(prec, fout, 64)
     for k in (0, 1, 31, 62, 63):
         f1 = s.encode_full(prec, srcs[k], 1)
         o1 = s.field(prec)
-        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        wd.wd_dslash_field(s.gauge, o1, f1, 0, 0, prec)
         assert np.array_equal(s.decode(prec, o1), multi[k]), k

@@ -72,7 +72,7 @@ def run(s, src, cbs, prec, nrhs):
     fin = wd.new_field(s.lat, prec, nrhs)
     fout = wd.new_field(s.lat, prec, nrhs)
     wd.wd_spinor_encode_full(s.lat, prec, nrhs, 1, fin, src[:nrhs].contiguous())
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, nrhs)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, prec, nrhs)
     out = torch.empty((nrhs, s.Vh, 4, 3, 2), dtype=torch.float64, device=DEV)
     wd.wd_spinor_decode(s.lat, prec, nrhs, out, fout)
     idx = torch.from_numpy(cbs).to(DEV)

@@ -46,7 +46,7 @@ def test_recon8_dslash_matches_oracle(dims, prec, dagger):
     _, po = oracle.split(dims, psi)
     fin = s.encode_full(prec, psi, 1)
     fout = s.field(prec)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, dagger, prec)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, dagger, prec)
     got = s.decode(prec, fout)
     ref = oracle.dslash_parity(dims, U, po, 0, dagger=bool(dagger))
     assert rel_l2(got, ref) <= TOL[prec]
@@ -66,12 +66,12 @@ def test_recon8_multi_rhs_equals_single_rhs(prec):
     srcs = wdinputs.spinor_gaussian(dims, 94, nrhs=3)
     fin = s.encode_full(prec, srcs, 1, nrhs=3)
     fout = s.field(prec, 3)
-    wd.wilson_dslash(s.gauge, fout, fin, 0, 0, prec, 3)
+    wd.wd_dslash_field(s.gauge, fout, fin, 0, 0, prec, 3)
     multi = s.decode(prec, fout, 3)
     for k in range(3):
         f1 = s.encode_full(prec, srcs[k], 1)
         o1 = s.field(prec)
-        wd.wilson_dslash(s.gauge, o1, f1, 0, 0, prec)
+        wd.wd_dslash_field(s.gauge, o1, f1, 0, 0, prec)
         assert np.array_equal(s.decode(prec, o1), multi[k])
 
 
@@ -117,7 +117,7 @@ def test_temporal_gauge_dslash_matches_oracle_on_the_fixed_field(recon, prec):
     for dagger in (0, 1):
         fin = s.encode_full(prec, psi, 1)
         fout = s.field(prec)
-        wd.wilson_dslash(s.gauge, fout, fin, 0, dagger, prec)
+        wd.wd_dslash_field(s.gauge, fout, fin, 0, dagger, prec)
         ref = oracle.dslash_parity(dims, Uf, po, 0, dagger=bool(dagger))
         assert rel_l2(s.decode(prec, fout), ref) <= TOL[prec], dagger
 

@@ -36,7 +36,7 @@ def test_first_launch_tunes_once_and_records_its_choice(tmp_path, monkeypatch, c
 
     def run():
         fout = s.field("f16", nrhs)
-        wd.wilson_dslash_basis(s.gauge, fout, fin, 0, 0, "f16", nrhs, UK)
+        wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 0, "f16", nrhs, UK)
         return s.decode("f16", fout, nrhs, basis=UK)
 
     first = run()

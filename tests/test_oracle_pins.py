@@ -282,6 +282,49 @@ def test_prepare_and_reconstruct_give_the_dense_solution():
     assert oracle.true_relres(dims, U, kappa, b, x_full) < 1e-14
 
 
+@pytest.mark.parametrize("tap", [True, False])
+def test_true_relres_is_the_dense_residual_at_non_solutions(tap):
+    """The checker behind every solver parity claim, ||b - (1 - kappa D) x|| /
+    ||b|| of the full system (Section 3), against the dense matrix of Eq. 1
+    at points that are not solutions: x = 0 gives exactly 1; x = the dense
+    solution plus a perturbation gives the dense residual norm (a dropped
+    square root, a missing normalisation by ||b||, a sign of kappa or a
+    residual of the Schur system alone would all fail here)."""
+    dims, kappa = (2, 4, 2, 6), 0.12
+    U = wdinputs.gauge_random(dims, 0.3, 111)
+    b = wdinputs.spinor_gaussian(dims, 112)
+    M = np.eye(12 * 96) - kappa * dense_hopping(dims, U, antiperiodic_t=tap)
+    bv = to_vec(b)
+    assert oracle.true_relres(dims, U, kappa, b, np.zeros_like(b), antiperiodic_t=tap) == 1.0
+    # x = b: residual kappa D b, whose norm is independent of the solve
+    expect = np.linalg.norm(bv - M @ bv) / np.linalg.norm(bv)
+    got = oracle.true_relres(dims, U, kappa, b, b, antiperiodic_t=tap)
+    assert abs(got - expect) <= 1e-14 * expect
+    # scaled b: the relative residual does not depend on the scale of b and x
+    got2 = oracle.true_relres(dims, U, kappa, 3.0 * b, 3.0 * b, antiperiodic_t=tap)
+    assert abs(got2 - expect) <= 1e-14 * expect
+    x_ref = np.linalg.solve(M, bv)
+    rng = np.random.default_rng(113)
+    for scale in (1e-3, 1e-7, 1e-11):
+        dx = scale * (rng.standard_normal(x_ref.shape) + 1j * rng.standard_normal(x_ref.shape))
+        xv = x_ref + dx
+        expect = np.linalg.norm(bv - M @ xv) / np.linalg.norm(bv)
+        got = oracle.true_relres(dims, U, kappa, b, from_vec(xv), antiperiodic_t=tap)
+        # the dense residual itself carries ~1e-16 * ||b|| of rounding
+        assert abs(got - expect) <= 1e-12 * expect + 1e-15, (scale, got, expect)
+        # and it is linear in the perturbation: ||M dx|| / ||b||
+        lin = np.linalg.norm(M @ dx) / np.linalg.norm(bv)
+        assert abs(got - lin) <= 1e-3 * lin + 1e-15
+    # the odd-site residual counts too: perturbing only the odd sites of the
+    # dense solution moves the result
+    even, odd = parity_masks(dims)
+    xv = x_ref.copy()
+    xv[odd] += 1e-6
+    expect = np.linalg.norm(bv - M @ xv) / np.linalg.norm(bv)
+    got = oracle.true_relres(dims, U, kappa, b, from_vec(xv), antiperiodic_t=tap)
+    assert abs(got - expect) <= 1e-9 * expect and expect > 1e-7
+
+
 @pytest.mark.parametrize("solver", ["bicgstab", "cgnr"])
 def test_solvers_match_dense_solve(solver):
     dims, kappa = (2, 4, 2, 6), 0.12
