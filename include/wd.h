@@ -241,6 +241,21 @@ wd_status wd_mat_pc_field(const wd_gauge *g, double kappa, void *out, const void
 wd_status wd_mdagm_field(const wd_gauge *g, double kappa, void *out, const void *in, void *tmp_odd,
                          void *tmp_even, wd_prec prec, int32_t nrhs, void *stream);
 
+/* mdagm for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out_e = M_hat^dagger M_hat in_e on canonical FP64 parity spinors, with no
+ * workspace argument.  Its four encoded scratch fields live in a static
+ * device array of 64 MiB that every GPU the library runs on holds until the
+ * process ends; (lattice, prec, nrhs) needing more than that
+ * (wd_operator_workspace_bytes > 64 MiB: for one RHS FP64 above Vh = 87,360,
+ * FP32 above Vh = 174,720, 16-bit above Vh = 322,624) are refused with
+ * WD_EINVAL.  The launch shape is the tuned one if already known, else the
+ * default (no tuning runs).  Allocates nothing.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU race, so the caller serialises them.
+ * Asynchronous on stream. */
+wd_status mdagm_noalloc(const wd_gauge *g, double kappa, double *out, const double *in, wd_prec prec,
+                        int32_t nrhs, void *stream);
+
 /* ---- solvers ------------------------------------------------------------------- */
 
 #define WD_SOLVER_BICGSTAB 0 /* BiCGstab on M_hat (Section 5.1) */

@@ -20,7 +20,7 @@ __all__ = [
     "wd_spinor_encode_basis", "wd_spinor_decode_basis", "wd_dslash_field", "wd_dslash_field_basis",
     "wd_mat_pc_field", "wd_mdagm_field", "wd_operator_workspace_bytes", "new_operator_workspace",
     "WD_BASIS_DEGRAND_ROSSI", "WD_BASIS_UKQCD",
-    "wilson_mat_pc", "mdagm", "gauge_fix_temporal", "wd_gauge_rotate_spinor", "WD_GAUGE_TEMPORAL",
+    "wilson_mat_pc", "mdagm", "mdagm_noalloc", "gauge_fix_temporal", "wd_gauge_rotate_spinor", "WD_GAUGE_TEMPORAL",
 ]
 
 
@@ -164,6 +164,12 @@ def wilson_mat_pc(gauge: Gauge, kappa: float, out, inp, dagger: int, prec, nrhs:
 def mdagm(gauge: Gauge, kappa: float, out, inp, prec, nrhs: int, workspace, stream=None):
     return check(lib().mdagm(gauge.handle, kappa, ptr(out), ptr(inp), prec_of(prec), nrhs, ptr(workspace),
                              workspace.numel(), stream_ptr(stream)), "mdagm")
+
+
+def mdagm_noalloc(gauge: Gauge, kappa: float, out, inp, prec, nrhs: int, stream=None):
+    """mdagm with its scratch in the library's static device array (no workspace)."""
+    return check(lib().mdagm_noalloc(gauge.handle, kappa, ptr(out), ptr(inp), prec_of(prec), nrhs,
+                                     stream_ptr(stream)), "mdagm_noalloc")
 
 
 def wd_dslash_field(gauge: Gauge, out, inp, out_parity: int, dagger: int, prec, nrhs: int = 1, stream=None):

@@ -87,6 +87,8 @@ def lib():
         L.wilson_mat_pc.restype = i32
         L.mdagm.argtypes = [vp, dbl, vp, vp, i32, i32, vp, sz, vp]
         L.mdagm.restype = i32
+        L.mdagm_noalloc.argtypes = [vp, dbl, vp, vp, i32, i32, vp]
+        L.mdagm_noalloc.restype = i32
         L.wd_dslash_field.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
         L.wd_dslash_field.restype = i32
         L.wd_dslash_field_basis.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp]

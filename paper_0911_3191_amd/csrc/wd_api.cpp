@@ -393,22 +393,33 @@ static wd_status check_canon_op(const wd_gauge* g, void* out, const void* in, wd
 // is encoded before anything is written to out.
 hipError_t canon_operator(const wd_gauge* g, int op, double kappa, double* out, const double* in,
                           int out_parity, int dagger, wd_prec prec, int nrhs, char* ws, size_t slot,
-                          hipStream_t s) {
+                          hipStream_t s, bool no_tune) {
   const Geom& geo = g->geom;
   Field fin = field_of(geo, ws, nrhs), fout = field_of(geo, ws + slot, nrhs);
   Field fodd = field_of(geo, ws + 2 * slot, nrhs), feven = field_of(geo, ws + 3 * slot, nrhs);
+  auto dslash = [&](Field o, Field i, int par, int dag, const Field* xpay, double a) {
+    DslashArgs d;
+    d.out = o;
+    d.in = i;
+    d.out_parity = par;
+    d.dagger = dag;
+    d.xpay = xpay;
+    d.a = a;
+    d.no_tune = no_tune ? 1 : 0;
+    return launch_dslash_ex(g, prec, d, s);
+  };
   hipError_t e = launch_spinor_encode(geo, prec, fin, in, s);
   if (e != hipSuccess) return e;
   if (op == 0) {
-    e = launch_dslash(g, prec, fout, fin, out_parity, dagger, nullptr, 0.0, s);
+    e = dslash(fout, fin, out_parity, dagger, nullptr, 0.0);
   } else {
     const double a = -kappa * kappa;
-    e = launch_dslash(g, prec, fodd, fin, 1, op == 1 ? dagger : 0, nullptr, 0.0, s);
-    if (e == hipSuccess)
-      e = launch_dslash(g, prec, op == 1 ? fout : feven, fodd, 0, op == 1 ? dagger : 0, &fin, a, s);
+    const int dag1 = op == 1 ? dagger : 0;
+    e = dslash(fodd, fin, 1, dag1, nullptr, 0.0);
+    if (e == hipSuccess) e = dslash(op == 1 ? fout : feven, fodd, 0, dag1, &fin, a);
     if (op == 2) {
-      if (e == hipSuccess) e = launch_dslash(g, prec, fodd, feven, 1, 1, nullptr, 0.0, s);
-      if (e == hipSuccess) e = launch_dslash(g, prec, fout, fodd, 0, 1, &feven, a, s);
+      if (e == hipSuccess) e = dslash(fodd, feven, 1, 1, nullptr, 0.0);
+      if (e == hipSuccess) e = dslash(fout, fodd, 0, 1, &feven, a);
     }
   }
   if (e != hipSuccess) return e;

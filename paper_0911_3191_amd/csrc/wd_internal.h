@@ -101,6 +101,9 @@ struct DslashArgs {
   const Field* enc_xh = nullptr;
   const Field* enc_rt = nullptr;
   int enc_set_rt = 0;
+  // 1: never run the autotuner for this launch (a tuned shape already cached
+  // is used, else the default); for callers that must not create events
+  int no_tune = 0;
 };
 hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 
@@ -218,9 +221,10 @@ wd_status solver_complete(wd_solver* h); // wait for it, reliable update if trig
 // workspace `ws` (four fields of `slot` bytes), canonical out: op 0 is the
 // hopping term D_{p,1-p}, op 1 M_hat (adjoint with dagger), op 2
 // M_hat^dagger M_hat.  Asynchronous on s.
+// no_tune: the dslash launches never run the autotuner.
 hipError_t canon_operator(const wd_gauge* g, int op, double kappa, double* out, const double* in,
                           int out_parity, int dagger, wd_prec prec, int nrhs, char* ws, size_t slot,
-                          hipStream_t s);
+                          hipStream_t s, bool no_tune = false);
 
 // ---- error reporting ------------------------------------------------------------
 void set_error(const std::string& msg);

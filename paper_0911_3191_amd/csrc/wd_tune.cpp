@@ -176,7 +176,7 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
     auto it = g_cache.find(k);
     if (it != g_cache.end()) return it->second;
   }
-  if (!tuning_enabled()) return default_cfg(prec, nrhs);
+  if (!tuning_enabled() || d.no_tune) return default_cfg(prec, nrhs);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return default_cfg(prec, nrhs);
