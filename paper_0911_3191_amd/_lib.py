@@ -11,7 +11,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwdslash.so")
+# WD_LIB_PATH selects another build of the same library (e.g. a sanitizer build)
+LIB_PATH = os.environ.get("WD_LIB_PATH") or os.path.join(HERE, "libwdslash.so")
 
 WD_OK, WD_NOT_CONVERGED = 0, 1
 WD_EINVAL, WD_ENOMEM, WD_EDEVICE, WD_EBREAKDOWN, WD_EUNSUPPORTED = -1, -2, -3, -4, -5

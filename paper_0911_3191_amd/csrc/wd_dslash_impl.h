@@ -525,6 +525,219 @@ __device__ __forceinline__ void gather_half16(const SpinorBuf<S>& b, int i, cx<f
   }
 }
 
+// ---- binary16 fields: SU(3) products as packed dot products -------------------
+// For binary16 storage the link rows a, b are binary16 (re, im) pairs as
+// stored, the third row is formed in binary32 from them and rounded once to
+// binary16, and the projected half spinor h = psi_up + i^n psi_dn is formed
+// with one packed binary16 add per complex number (one rounding).  Each real
+// part of U h is then a chain of three v_dot2_f32_f16: two exact binary16
+// products per instruction, summed in binary32:
+//   (U h).re     = sum_b dot2(u_ab, conj(h_b)),  (U h).im     = sum_b dot2(u_ab, swap(h_b)),
+//   (U^dag h).re = sum_b dot2(u_ba, h_b),        (U^dag h).im = sum_b dot2(u_ba, -i h_b),
+// with swap(h) = (h.im, h.re).  The link is used exactly as stored; each of
+// the two forms of h a hop needs is one packed add whose operand modifiers
+// carry the phase i^n and the form.  The neighbour's norm and the boundary
+// sign enter in the binary32 accumulation, as for the other formats.
+// Complex numbers are handled as 32-bit words (re in the low half).  The
+// packed adds and the first product of each chain are written out as
+// instructions so that each form is one instruction (the compiler would
+// otherwise share a + i^n b between the forms and fix it up afterwards) and a
+// chain needs no zeroed accumulator.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2 as_h2(uint32_t w) { return __builtin_bit_cast(h2, w); }
+__device__ __forceinline__ uint32_t wswap(uint32_t w) { return (w >> 16) | (w << 16); }
+__device__ __forceinline__ uint32_t wconj(uint32_t w) { return w ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t pack_w(float re, float im) {
+  return __builtin_bit_cast(uint32_t, h2{(_Float16)re, (_Float16)im});
+}
+// c + a.lo b.lo + a.hi b.hi in binary32; dot2z: the same with c = 0
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2(as_h2(a), as_h2(b), c, false);
+}
+__device__ __forceinline__ float dot2z(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// -i w = (w.im, -w.re)
+__device__ __forceinline__ uint32_t wmi(uint32_t w) {
+  uint32_t r;
+  asm("v_pk_add_f16 %0, %1, 0 op_sel:[1,0] op_sel_hi:[0,0] neg_lo:[0,0] neg_hi:[1,0]" : "=v"(r) : "v"(w));
+  return r;
+}
+
+// Forms of h = a + i^N b, one packed add each: F = 0: h, 1: conj(h),
+// 2: swap(h), 3: -i h.
+constexpr int kFormId = 0, kFormConj = 1, kFormSwap = 2, kFormMi = 3;
+template <int F, int N>
+__device__ __forceinline__ uint32_t pk_form(uint32_t a, uint32_t b) {
+  constexpr int n = ((N % 4) + 4) % 4;
+  uint32_t r;
+  if constexpr (F == 0 && n == 0)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,0] neg_hi:[0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 0 && n == 1)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 0 && n == 2)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,1] neg_hi:[0,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 0 && n == 3)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,0] neg_hi:[0,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 1 && n == 0)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,0] neg_hi:[1,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 1 && n == 1)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[1,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 1 && n == 2)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,1] neg_hi:[1,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 1 && n == 3)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,0] neg_hi:[1,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 2 && n == 0)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,0] neg_hi:[0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 2 && n == 1)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,0] neg_hi:[0,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 2 && n == 2)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[0,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 2 && n == 3)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 3 && n == 0)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,0] neg_hi:[1,1]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 3 && n == 1)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,0] neg_hi:[1,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 3 && n == 2)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[1,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (F == 3 && n == 3)
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[1,1]" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+struct Link16 {
+  uint32_t u[3][3];  // (re, im) binary16 pairs
+};
+
+// Rows a, b of a binary16 12-real link as stored; third row c = (a x b)^*
+// in binary32 from the stored values, rounded once to binary16.
+template <int AUX>
+__device__ __forceinline__ void gather_link16(const char* links, int64_t stride, int par, int mu, int i,
+                                              Link16& L) {
+  const uint32_t cbytes = (uint32_t)(stride * 8);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(links + ((int64_t)(par * 4 + mu) * 3) * stride * 8, cbytes * 3);
+  const uint32_t vo = (uint32_t)i * 8u;
+  uint32_t w[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint2 c = bload8<AUX>(rs, vo, k * cbytes);
+    w[2 * k] = c.x;
+    w[2 * k + 1] = c.y;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    L.u[0][j] = w[j];
+    L.u[1][j] = w[3 + j];
+  }
+  // c_j = conj(a_j1 b_j2 - a_j2 b_j1): binary32 products of binary16 values
+  // (mixed-precision FMAs read the halves in place)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const h2 p = as_h2(w[(j + 1) % 3]), q = as_h2(w[3 + (j + 2) % 3]);
+    const h2 u = as_h2(w[(j + 2) % 3]), v = as_h2(w[3 + (j + 1) % 3]);
+    const float re = fmar((float)p.x, (float)q.x, fmar(-(float)p.y, (float)q.y,
+                          fmar(-(float)u.x, (float)v.x, (float)u.y * (float)v.y)));
+    const float im = fmar((float)u.x, (float)v.y, fmar((float)u.y, (float)v.x,
+                          fmar(-(float)p.x, (float)q.y, -((float)p.y * (float)q.x))));
+    L.u[2][j] = pack_w(re, im);
+  }
+}
+
+// A binary32 link (8-real rebuild, unit matrix) in the binary16 operand form.
+__device__ __forceinline__ void link16_from(const Link<float>& U, Link16& L) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) L.u[a][b] = pack_w(U.u[a][b].re, U.u[a][b].im);
+}
+
+// Row a of W h for W = U (DAG_LINK false; forms f1 = conj(h), f2 = swap(h))
+// or W = U^dagger (forms f1 = h, f2 = -i h).
+template <bool DAG_LINK>
+__device__ __forceinline__ cx<float> su3_row16(const Link16& U, int a, const uint32_t (&f1)[3],
+                                               const uint32_t (&f2)[3]) {
+  cx<float> w;
+  if constexpr (!DAG_LINK) {
+    w.re = dot2(U.u[a][2], f1[2], dot2(U.u[a][1], f1[1], dot2z(U.u[a][0], f1[0])));
+    w.im = dot2(U.u[a][2], f2[2], dot2(U.u[a][1], f2[1], dot2z(U.u[a][0], f2[0])));
+  } else {
+    w.re = dot2(U.u[2][a], f1[2], dot2(U.u[1][a], f1[1], dot2z(U.u[0][a], f1[0])));
+    w.im = dot2(U.u[2][a], f2[2], dot2(U.u[1][a], f2[1], dot2z(U.u[0][a], f2[0])));
+  }
+  return w;
+}
+
+// One hop from a packed binary16 neighbour (in units of its norm): project,
+// multiply by W, expand to four spins and accumulate (as hop16 / mul_acc).
+template <int MU, int S, bool DAG_LINK, int BASIS>
+__device__ __forceinline__ void hop16d(Spinor<float>& acc, const Raw16& psi, const Link16& U, float scale) {
+  using G = GammaB<MU, BASIS>;
+  constexpr int sh = (S < 0) ? 2 : 0;
+  constexpr int F1 = DAG_LINK ? kFormId : kFormConj, F2 = DAG_LINK ? kFormMi : kFormSwap;
+  uint32_t f1[2][3], f2[2][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const uint32_t a0 = psi.w[c], b0 = psi.w[3 * (2 + G::P0) + c];
+    const uint32_t a1 = psi.w[3 + c], b1 = psi.w[3 * (2 + G::P1) + c];
+    f1[0][c] = pk_form<F1, G::PH0 + sh>(a0, b0);
+    f2[0][c] = pk_form<F2, G::PH0 + sh>(a0, b0);
+    f1[1][c] = pk_form<F1, G::PH1 + sh>(a1, b1);
+    f2[1][c] = pk_form<F2, G::PH1 + sh>(a1, b1);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int lo = 2 + (k == 0 ? G::P0 : G::P1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const cx<float> w = su3_row16<DAG_LINK>(U, a, f1[k], f2[k]);
+      acc.v[k][a] = acc.v[k][a] + scale * w;
+      const cx<float> wl = (k == 0) ? iph<sh - G::PH0 + 4>(w) : iph<sh - G::PH1 + 4>(w);
+      acc.v[lo][a] = acc.v[lo][a] + scale * wl;
+    }
+  }
+}
+
+// Temporal hop in the UKQCD basis on binary16 fields: the two spins the
+// projector keeps (BASE, BASE + 1; packed words w) times W, added to those
+// spins; the factor 2 is in scale.
+template <bool DAG_LINK, int BASE>
+__device__ __forceinline__ void mul_acc_half16(Spinor<float>& acc, const uint32_t (&w)[6], const Link16& U,
+                                               float scale) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    uint32_t f1[3], f2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint32_t h = w[3 * k + c];
+      f1[c] = DAG_LINK ? h : wconj(h);
+      f2[c] = DAG_LINK ? wmi(h) : wswap(h);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc.v[BASE + k][a] = acc.v[BASE + k][a] + scale * su3_row16<DAG_LINK>(U, a, f1, f2);
+  }
+}
+
+// Spins BASE, BASE + 1 of a binary16 neighbour as packed words (see
+// gather_half16), with the factor that turns stored values into reals.
+template <int BASE>
+__device__ __forceinline__ void gather_half16w(const SpinorBuf<SF16>& b, int i, uint32_t (&w)[6], float& scale) {
+  const uint32_t vo = (uint32_t)i * 16u;
+  scale = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.norms, (uint32_t)i * 4u, 0, 0));
+  if constexpr (BASE == 0) {
+    const uint4 c0 = bload16(b.chunks, vo, 0);
+    const uint2 c1 = bload8(b.chunks, vo, b.chunk_bytes);
+    w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w; w[4] = c1.x; w[5] = c1.y;
+  } else {
+    const uint2 c1 = bload8(b.chunks, vo + 8u, b.chunk_bytes);
+    const uint4 c2 = bload16(b.chunks, vo, 2 * b.chunk_bytes);
+    w[0] = c1.x; w[1] = c1.y; w[2] = c2.x; w[3] = c2.y; w[4] = c2.z; w[5] = c2.w;
+  }
+}
+
 // ---- LDS staging of x/y neighbours (16-bit formats) ------------------------------
 // A workgroup of the slab mapping owns 256 consecutive slab positions, i.e.
 // whole or partial rows of Lxh sites with y fastest.  Its x-neighbours lie in
@@ -620,6 +833,28 @@ __device__ __forceinline__ void hop_fence(Spinor<R> (&acc)[NR]) {
       }
 }
 
+// Link of (par, mu) at site i for binary16 fields, in the dot-product form:
+// 12 reals as stored (Appendix A.1), 8 reals rebuilt in binary32 (Appendix
+// A.2), or the unit matrix (temporal gauge).
+template <class S, int RECON, int AUX>
+__device__ __forceinline__ void link_of16(const DslashGeom& g, const char* links, int par, int mu, int i, bool unit,
+                                          Link16& L) {
+  if constexpr (RECON == 8) {
+    Link<float> U;
+    if (unit) unit_link(U);
+    else gather_link<S, RECON, AUX>(g, links, par, mu, i, U);
+    link16_from(U, L);
+  } else {
+    if (unit) {
+      Link<float> U;
+      unit_link(U);
+      link16_from(U, L);
+    } else {
+      gather_link16<AUX>(links, g.stride, par, mu, i, L);
+    }
+  }
+}
+
 // Both hops of direction MU for the NR right-hand sides of this thread.
 template <class S, int MU, bool DAGGER, int NR, int RECON, bool LDS, int BASIS>
 __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], const DslashGeom& g,
@@ -667,7 +902,27 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
     unit_b = g.tgauge && X[3] != 0;
   }
   // forward: (1 - gamma_mu) U_x^mu psi(x + mu); adjoint: (1 + gamma_mu)
-  {
+  if constexpr (S::prec == WD_HALF_F16) {
+    Link16 U;
+    link_of16<S, RECON, (NR == 1 ? kStream : 0)>(g, links, p, MU, cb, unit_f, U);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if constexpr (MU == 3 && BASIS == kBasisUK) {
+        constexpr int BASE = DAGGER ? 0 : 2;
+        uint32_t w[6];
+        float s16;
+        gather_half16w<BASE>(in[k], nf, w, s16);
+        mul_acc_half16<false, BASE>(acc[k], w, U, flip_f ? -2.0f * s16 : 2.0f * s16);
+      } else {
+        Raw16 psi;
+        float sc;
+        if (LDS && lf >= 0) lds_gather16<S>(lc, k, lf, psi, sc);
+        else gather_spinor16<S>(in[k], nf, psi, sc);
+        if (flip_f) sc = -sc;
+        hop16d<MU, DAGGER ? +1 : -1, false, BASIS>(acc[k], psi, U, sc);
+      }
+    }
+  } else {
     Link<R> U;
     if (unit_f) unit_link(U);
     else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, p, MU, cb, U);
@@ -703,7 +958,27 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
   // FP64 spinors are large enough that one hop's loads fill the registers
   if constexpr (S::prec == WD_FP64) hop_fence<R, NR>(acc);
   // backward: (1 + gamma_mu) U_{x-mu}^mu^dagger psi(x - mu); adjoint: (1 - gamma_mu)
-  {
+  if constexpr (S::prec == WD_HALF_F16) {
+    Link16 U;
+    link_of16<S, RECON, (NR == 1 ? kStream : 0)>(g, links, 1 - p, MU, nb, unit_b, U);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if constexpr (MU == 3 && BASIS == kBasisUK) {
+        constexpr int BASE = DAGGER ? 2 : 0;
+        uint32_t w[6];
+        float s16;
+        gather_half16w<BASE>(in[k], nb, w, s16);
+        mul_acc_half16<true, BASE>(acc[k], w, U, flip_b ? -2.0f * s16 : 2.0f * s16);
+      } else {
+        Raw16 psi;
+        float sc;
+        if (LDS && lb >= 0) lds_gather16<S>(lc, k, lb, psi, sc);
+        else gather_spinor16<S>(in[k], nb, psi, sc);
+        if (flip_b) sc = -sc;
+        hop16d<MU, DAGGER ? -1 : +1, true, BASIS>(acc[k], psi, U, sc);
+      }
+    }
+  } else {
     Link<R> U;
     if (unit_b) unit_link(U);
     else gather_link<S, RECON, (NR == 1 ? kStream : 0)>(g, links, 1 - p, MU, nb, U);
@@ -756,6 +1031,143 @@ struct EncView {
   int set_rt;
 };
 
+// The epilogue fuses its products explicitly.  Left to the compiler, x + a*acc
+// (x itself a product once decoded from 16 bits) and the two terms of a
+// complex product can each be fused either way, and kernels that inline the
+// same code have been compiled to different choices, so results depended on
+// the launch shape.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// re + i im += conj(u) v, one term at a time
+template <class R>
+__device__ __forceinline__ void acc_cdotc(R& re, R& im, const cx<R>& u, const cx<R>& v) {
+  re = fmad(u.re, v.re, re);
+  re = fmad(u.im, v.im, re);
+  im = fmad(u.re, v.im, im);
+  im = fmad(-u.im, v.re, im);
+}
+// nn += |u|^2
+template <class R, class T>
+__device__ __forceinline__ void acc_norm(T& nn, const cx<R>& u) {
+  nn = fmad(T(u.re), T(u.re), nn);
+  nn = fmad(T(u.im), T(u.im), nn);
+}
+
+// Per right-hand side after the hops: xpay, residual, store (or re-encode)
+// and the fused FP64 partial dot products of one workgroup.  Every thread of
+// the block calls it for the same r (the reductions synchronise the block).
+template <class S, bool XPAY, int DOT, class S2>
+__device__ __forceinline__ void finish_rhs(const DslashGeom& g, Spinor<typename S::real>& acc, int r, int cb,
+                                           bool valid, int pid, FieldView out, FieldView xs, FieldView ys,
+                                           typename S::real a, double* __restrict__ partials, const EncView& enc) {
+  using R = typename S::real;
+  Spinor<R> x;
+  if (valid) {
+    if constexpr (XPAY) {
+      load_spinor<S>(xs, r, cb, x);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          acc.v[s][c] = {fmad(a, acc.v[s][c].re, x.v[s][c].re), fmad(a, acc.v[s][c].im, x.v[s][c].im)};
+    }
+    if constexpr (DOT == DOT_RES || DOT == DOT_RES_ENC) {
+      Spinor<R> b;
+      load_spinor<S>(ys, r, cb, b);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.v[s][c] = b.v[s][c] - acc.v[s][c];
+    }
+    if constexpr (DOT != DOT_RES_ENC) {
+      if (g.out_nt) store_spinor<S, true>(out, r, cb, acc);
+      else store_spinor<S>(out, r, cb, acc);
+    }
+  }
+  if constexpr (DOT == DOT_RES_ENC) {
+    using R2 = typename S2::real;
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      Spinor<R2> e, z, t;
+      double nn = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc_norm(nn, acc.v[s][c]);
+          e.v[s][c] = {static_cast<R2>(acc.v[s][c].re), static_cast<R2>(acc.v[s][c].im)};
+          z.v[s][c] = {R2(0), R2(0)};
+        }
+      store_spinor<S2>(enc.rh, r, cb, e);
+      store_spinor<S2>(enc.xh, r, cb, z);
+      if (enc.set_rt) store_spinor<S2>(enc.rt, r, cb, e);
+      // the dots see the stored (re-encoded) residual
+      load_spinor<S2>(enc.rh, r, cb, e);
+      load_spinor<S2>(enc.rt, r, cb, t);
+      R2 n2 = 0, re = 0, im = 0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc_norm(n2, e.v[s][c]);
+          acc_cdotc(re, im, t.v[s][c], e.v[s][c]);
+        }
+      d[0] = nn;
+      d[1] = n2;
+      d[2] = re;
+      d[3] = im;
+    }
+    const int nb = (g.slab ? 8 : 1) * g.site_blocks;
+    block_sum_store<4>(d, partials + ((int64_t)r * nb + pid) * kMaxDot);
+  }
+  if constexpr (DOT != DOT_NONE && DOT != DOT_RES_ENC) {
+    const int nb = (g.slab ? 8 : 1) * g.site_blocks;
+    double* part = partials + ((int64_t)r * nb + pid) * kMaxDot;
+    if constexpr (DOT == DOT_YO) {
+      double d[2] = {0.0, 0.0};
+      if (valid) {
+        Spinor<R> y;
+        load_spinor<S>(ys, r, cb, y);
+        R re = 0, im = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc_cdotc(re, im, y.v[s][c], acc.v[s][c]);
+        d[0] = re;
+        d[1] = im;
+      }
+      block_sum_store<2>(d, part);
+    } else if constexpr (DOT == DOT_OX) {
+      double d[3] = {0.0, 0.0, 0.0};
+      if (valid) {
+        R re = 0, im = 0, nn = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            acc_cdotc(re, im, acc.v[s][c], x.v[s][c]);
+            acc_norm(nn, acc.v[s][c]);
+          }
+        d[0] = re;
+        d[1] = im;
+        d[2] = nn;
+      }
+      block_sum_store<3>(d, part);
+    } else {
+      double d[1] = {0.0};
+      if (valid) {
+        R nn = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc_norm(nn, acc.v[s][c]);
+        d[0] = nn;
+      }
+      block_sum_store<1>(d, part);
+    }
+  }
+}
+
 template <class S, bool DAGGER, bool XPAY, int DOT, int NR, int RECON, bool LDS, int BASIS, class S2 = S>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char* __restrict__ links,
                                                        FieldView out, FieldView in, FieldView xs,
@@ -779,9 +1191,11 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     }
     if (site_block >= g.site_blocks || group >= g.ngroups) return;
     pid = xcd * g.site_blocks + site_block;
-    // position in this XCD's slab: sub-slab (slowest), t, z, y, x/2 (fastest)
-    const int s_local = site_block * blockDim.x + threadIdx.x;
-    valid = s_local < (g.Vh >> 3);
+    // position in this XCD's slab: sub-slab (slowest), t, z, y, x/2 (fastest);
+    // a thread past the end works on the last site and stores nothing
+    const int s_raw = site_block * blockDim.x + threadIdx.x;
+    valid = s_raw < (g.Vh >> 3);
+    const int s_local = valid ? s_raw : (g.Vh >> 3) - 1;
     const int sub = (int)fdiv((uint32_t)s_local, g.div_sub);
     const int r1 = s_local - sub * g.sub_sites;
     X3 = (int)fdiv((uint32_t)r1, g.div_sub_t);
@@ -802,6 +1216,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     pid = site_block;
     cb = site_block * blockDim.x + threadIdx.x;
     valid = cb < g.Vh;
+    if (!valid) cb = g.Vh - 1;  // works on the last site and stores nothing
     const int row = (int)fdiv((uint32_t)cb, g.div_lxh);
     xh = cb - row * g.Lxh;
     const int zt = (int)fdiv((uint32_t)row, g.div_ly);
@@ -839,8 +1254,8 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     int base;
     lds_stage<S, NR>(g, xcd, site_block, sb, on, chunks, norms, rowbase, &base);
     __syncthreads();
-    const int s_local = site_block * blockDim.x + threadIdx.x;
-    lc = LdsCtx{chunks, norms, g.lds_cap, base, (int)fdiv((uint32_t)s_local, g.div_lxh), X1 - (X1 / g.suby) * g.suby};
+    const int s_lds = valid ? site_block * (int)blockDim.x + (int)threadIdx.x : (g.Vh >> 3) - 1;
+    lc = LdsCtx{chunks, norms, g.lds_cap, base, (int)fdiv((uint32_t)s_lds, g.div_lxh), X1 - (X1 / g.suby) * g.suby};
   }
 
   Spinor<R> acc[NR];
@@ -850,7 +1265,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[k].v[s][c] = {R(0), R(0)};
-  if (valid) {
+  {
     // coordinates of the output site (cb, parity p)
     const int row = X1 + g.L[1] * (X2 + g.L[2] * X3);
     const int X[4] = {2 * xh + ((p + X1 + X2 + X3) & 1), X1, X2, X3};
@@ -870,119 +1285,160 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(DslashGeom g, const char
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     if (!on[k]) continue;  // uniform across the block
-    Spinor<R> x;
-    if (valid) {
-      if constexpr (XPAY) {
-        load_spinor<S>(xs, rhs[k], cb, x);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[k].v[s][c] = x.v[s][c] + a * acc[k].v[s][c];
-      }
-      if constexpr (DOT == DOT_RES || DOT == DOT_RES_ENC) {
-        Spinor<R> b;
-        load_spinor<S>(ys, rhs[k], cb, b);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[k].v[s][c] = b.v[s][c] - acc[k].v[s][c];
-      }
-      if constexpr (DOT != DOT_RES_ENC) {
-        if (g.out_nt) store_spinor<S, true>(out, rhs[k], cb, acc[k]);
-        else store_spinor<S>(out, rhs[k], cb, acc[k]);
-      }
+    finish_rhs<S, XPAY, DOT, S2>(g, acc[k], rhs[k], cb, valid, pid, out, xs, ys, a, partials, enc);
+  }
+}
+
+// ---- binary16, one thread per site for every right-hand side -----------------
+// Neighbour indices, boundary signs and unit-link flags of direction MU for
+// the output site (as computed inside hop_pair).
+struct HopIdx {
+  int nf, nb;
+  bool flip_f, flip_b, unit_f, unit_b;
+};
+template <int MU>
+__device__ __forceinline__ HopIdx hop_index(const DslashGeom& g, int xh, int row, const int (&X)[4]) {
+  HopIdx h;
+  h.flip_f = h.flip_b = h.unit_f = h.unit_b = false;
+  if constexpr (MU == 0) {
+    const int xf = (X[0] + 1 == g.L[0]) ? 0 : X[0] + 1;
+    const int xb = (X[0] == 0) ? g.L[0] - 1 : X[0] - 1;
+    h.nf = (xf >> 1) + g.Lxh * row;
+    h.nb = (xb >> 1) + g.Lxh * row;
+  } else {
+    int step = 1;
+    if constexpr (MU >= 2) step *= g.L[1];
+    if constexpr (MU == 3) step *= g.L[2];
+    const int rf = (X[MU] + 1 == g.L[MU]) ? row - (g.L[MU] - 1) * step : row + step;
+    const int rb = (X[MU] == 0) ? row + (g.L[MU] - 1) * step : row - step;
+    h.nf = xh + g.Lxh * rf;
+    h.nb = xh + g.Lxh * rb;
+    if constexpr (MU == 3) {
+      h.flip_f = g.tap && (X[3] == g.L[3] - 1);
+      h.flip_b = g.tap && (X[3] == 0);
+      h.unit_f = g.tgauge && X[3] != g.L[3] - 1;
+      h.unit_b = g.tgauge && X[3] != 0;
     }
-    if constexpr (DOT == DOT_RES_ENC) {
-      using R2 = typename S2::real;
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
-      if (valid) {
-        Spinor<R2> e, z, t;
-        double nn = 0.0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
-            e.v[s][c] = {static_cast<R2>(acc[k].v[s][c].re), static_cast<R2>(acc[k].v[s][c].im)};
-            z.v[s][c] = {R2(0), R2(0)};
-          }
-        store_spinor<S2>(enc.rh, rhs[k], cb, e);
-        store_spinor<S2>(enc.xh, rhs[k], cb, z);
-        if (enc.set_rt) store_spinor<S2>(enc.rt, rhs[k], cb, e);
-        // the dots see the stored (re-encoded) residual
-        load_spinor<S2>(enc.rh, rhs[k], cb, e);
-        load_spinor<S2>(enc.rt, rhs[k], cb, t);
-        R2 n2 = 0, re = 0, im = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            n2 += e.v[s][c].re * e.v[s][c].re + e.v[s][c].im * e.v[s][c].im;
-            const cx<R2> q = cmulc(t.v[s][c], e.v[s][c]);
-            re += q.re;
-            im += q.im;
-          }
-        d[0] = nn;
-        d[1] = n2;
-        d[2] = re;
-        d[3] = im;
-      }
-      const int nb = (g.slab ? 8 : 1) * g.site_blocks;
-      block_sum_store<4>(d, partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot);
+  }
+  return h;
+}
+
+// Both hops of direction MU for one right-hand side, links given.
+template <int MU, bool DAGGER, int BASIS>
+__device__ __forceinline__ void hop_pair16(Spinor<float>& acc, const SpinorBuf<SF16>& ib, const HopIdx& h,
+                                           const Link16& Uf, const Link16& Ub) {
+  if constexpr (MU == 3 && BASIS == kBasisUK) {
+    constexpr int BF = DAGGER ? 0 : 2, BB = DAGGER ? 2 : 0;
+    uint32_t w[6];
+    float s16;
+    gather_half16w<BF>(ib, h.nf, w, s16);
+    mul_acc_half16<false, BF>(acc, w, Uf, h.flip_f ? -2.0f * s16 : 2.0f * s16);
+    gather_half16w<BB>(ib, h.nb, w, s16);
+    mul_acc_half16<true, BB>(acc, w, Ub, h.flip_b ? -2.0f * s16 : 2.0f * s16);
+  } else {
+    Raw16 psi;
+    float sc;
+    gather_spinor16<SF16>(ib, h.nf, psi, sc);
+    hop16d<MU, DAGGER ? +1 : -1, false, BASIS>(acc, psi, Uf, h.flip_f ? -sc : sc);
+    gather_spinor16<SF16>(ib, h.nb, psi, sc);
+    hop16d<MU, DAGGER ? -1 : +1, true, BASIS>(acc, psi, Ub, h.flip_b ? -sc : sc);
+  }
+}
+
+template <int MU>
+__device__ __forceinline__ void link_pair16(const DslashGeom& g, const char* links, int p, int cb, const HopIdx& h,
+                                            Link16& Uf, Link16& Ub) {
+  link_of16<SF16, 12, 0>(g, links, p, MU, cb, h.unit_f, Uf);
+  link_of16<SF16, 12, 0>(g, links, 1 - p, MU, h.nb, h.unit_b, Ub);
+}
+
+// One thread computes one output site for every right-hand side of the
+// launch, one after another: the site's eight links (12 reals, binary16) are
+// gathered once and held in registers for all of them, and only one
+// right-hand side's neighbours are in flight at a time.  The workgroups
+// running together on an XCD then share a working set of one right-hand side
+// per site instead of all of them, so the t- and z-neighbours fetched by one
+// workgroup are still in L2 when the next needs them, and each link is read
+// once per launch.  Sites map to workgroups as in dslash_kernel with a single
+// RHS group; the arithmetic per right-hand side is that of dslash_kernel, so
+// results are bitwise the same.
+template <bool DAGGER, bool XPAY, int DOT, int BASIS, class S2 = SF16>
+__global__ void __launch_bounds__(kBlock) dslash16_rloop_kernel(DslashGeom g, const char* __restrict__ links,
+                                                               FieldView out, FieldView in, FieldView xs,
+                                                               FieldView ys, float a, int p,
+                                                               const int* __restrict__ sel,
+                                                               double* __restrict__ partials, EncView enc) {
+  const int xcd = blockIdx.x & 7;
+  const int j = blockIdx.x >> 3;
+  int site_block, pid, cb;
+  int xh = 0, X1 = 0, X2 = 0, X3 = 0;
+  bool valid;
+  if (g.slab) {
+    site_block = j;
+    if (site_block >= g.site_blocks) return;
+    pid = xcd * g.site_blocks + site_block;
+    const int s_raw = site_block * blockDim.x + threadIdx.x;
+    valid = s_raw < (g.Vh >> 3);
+    const int s_local = valid ? s_raw : (g.Vh >> 3) - 1;
+    const int sub = (int)fdiv((uint32_t)s_local, g.div_sub);
+    const int r1 = s_local - sub * g.sub_sites;
+    X3 = (int)fdiv((uint32_t)r1, g.div_sub_t);
+    const int r2 = r1 - X3 * g.sub_t_sites;
+    const int zl = (int)fdiv((uint32_t)r2, g.div_sub_plane);
+    const int r3 = r2 - zl * g.sub_plane;
+    const int yl = (int)fdiv((uint32_t)r3, g.div_lxh);
+    xh = r3 - yl * g.Lxh;
+    X1 = sub * (g.L[1] / g.nsub) + yl;
+    X2 = xcd * (g.L[2] >> 3) + zl;
+    cb = xh + g.Lxh * (X1 + g.L[1] * (X2 + g.L[2] * X3));
+  } else {
+    const int per = (g.site_blocks + 7) >> 3;
+    const int L = xcd * per + j;
+    if (j >= per || L >= g.site_blocks) return;
+    site_block = L;
+    pid = site_block;
+    cb = site_block * blockDim.x + threadIdx.x;
+    valid = cb < g.Vh;
+    if (!valid) cb = g.Vh - 1;
+    const int row = (int)fdiv((uint32_t)cb, g.div_lxh);
+    xh = cb - row * g.Lxh;
+    const int zt = (int)fdiv((uint32_t)row, g.div_ly);
+    X1 = row - zt * g.L[1];
+    X3 = (int)fdiv((uint32_t)zt, g.div_lz);
+    X2 = zt - X3 * g.L[2];
+  }
+  const int row = X1 + g.L[1] * (X2 + g.L[2] * X3);
+  const int X[4] = {2 * xh + ((p + X1 + X2 + X3) & 1), X1, X2, X3};
+  const HopIdx h0 = hop_index<0>(g, xh, row, X), h1 = hop_index<1>(g, xh, row, X);
+  const HopIdx h2 = hop_index<2>(g, xh, row, X), h3 = hop_index<3>(g, xh, row, X);
+  Link16 Uf[4], Ub[4];
+  link_pair16<0>(g, links, p, cb, h0, Uf[0], Ub[0]);
+  link_pair16<1>(g, links, p, cb, h1, Uf[1], Ub[1]);
+  link_pair16<2>(g, links, p, cb, h2, Uf[2], Ub[2]);
+  link_pair16<3>(g, links, p, cb, h3, Uf[3], Ub[3]);
+  for (int slot = 0; slot < g.nrhs; ++slot) {
+    int r;
+    if (g.mapped) {
+      r = sel[slot];
+    } else {
+      r = slot;
+      if (sel && !sel[slot]) continue;  // uniform across the block
     }
-    if constexpr (DOT != DOT_NONE && DOT != DOT_RES_ENC) {
-      const int nb = (g.slab ? 8 : 1) * g.site_blocks;
-      double* part = partials + ((int64_t)rhs[k] * nb + pid) * kMaxDot;
-      if constexpr (DOT == DOT_YO) {
-        double d[2] = {0.0, 0.0};
-        if (valid) {
-          Spinor<R> y;
-          load_spinor<S>(ys, rhs[k], cb, y);
-          R re = 0, im = 0;
+    const SpinorBuf<SF16> ib = spinor_buf<SF16>(in, r);
+    Spinor<float> acc[1];
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<R> t = cmulc(y.v[s][c], acc[k].v[s][c]);
-              re += t.re;
-              im += t.im;
-            }
-          d[0] = re;
-          d[1] = im;
-        }
-        block_sum_store<2>(d, part);
-      } else if constexpr (DOT == DOT_OX) {
-        double d[3] = {0.0, 0.0, 0.0};
-        if (valid) {
-          R re = 0, im = 0, nn = 0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<R> t = cmulc(acc[k].v[s][c], x.v[s][c]);
-              re += t.re;
-              im += t.im;
-              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
-            }
-          d[0] = re;
-          d[1] = im;
-          d[2] = nn;
-        }
-        block_sum_store<3>(d, part);
-      } else {
-        double d[1] = {0.0};
-        if (valid) {
-          R nn = 0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              nn += acc[k].v[s][c].re * acc[k].v[s][c].re + acc[k].v[s][c].im * acc[k].v[s][c].im;
-          d[0] = nn;
-        }
-        block_sum_store<1>(d, part);
-      }
-    }
+      for (int c = 0; c < 3; ++c) acc[0].v[s][c] = {0.0f, 0.0f};
+    hop_pair16<0, DAGGER, BASIS>(acc[0], ib, h0, Uf[0], Ub[0]);
+    hop_fence<float, 1>(acc);
+    hop_pair16<1, DAGGER, BASIS>(acc[0], ib, h1, Uf[1], Ub[1]);
+    hop_fence<float, 1>(acc);
+    hop_pair16<2, DAGGER, BASIS>(acc[0], ib, h2, Uf[2], Ub[2]);
+    hop_fence<float, 1>(acc);
+    hop_pair16<3, DAGGER, BASIS>(acc[0], ib, h3, Uf[3], Ub[3]);
+    hop_fence<float, 1>(acc);
+    finish_rhs<SF16, XPAY, DOT, S2>(g, acc[0], r, cb, valid, pid, out, xs, ys, a, partials, enc);
   }
 }
 
@@ -1115,6 +1571,55 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   }
 }
 
+template <bool DAGGER, bool XPAY, int BASIS>
+static void launch_rloop_dot(int dot, unsigned grid, hipStream_t s, const DslashGeom& g, const char* links,
+                             FieldView fo, FieldView fi, FieldView fx, FieldView fy, float a, int p,
+                             const int* sel, double* partials, EncView enc) {
+  if constexpr (BASIS == kBasisDR || !XPAY) {
+    dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+  } else {
+    switch (dot) {
+      case DOT_YO:
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_YO, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        break;
+      case DOT_OX:
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OX, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        break;
+      case DOT_OO:
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OO, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        break;
+      default:
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+    }
+  }
+}
+
+// The RHS-loop launch (binary16, 12-real links): one RHS group covering the
+// whole batch, so the grid is one workgroup per site block.
+template <int BASIS>
+static void launch_rloop(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
+  const int n = d.rhs_map ? d.n_map : d.out.nrhs;
+  LaunchCfg c = cfg;
+  c.nr = n;  // a single RHS group
+  DslashGeom g = make_dgeom(gg->geom, n, c);
+  g.mapped = d.rhs_map ? 1 : 0;
+  g.tgauge = gg->tgauge;
+  const char* links = static_cast<const char*>(gg->link[WD_HALF_F16]);
+  const unsigned grid = grid_blocks(g);
+  FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
+  const float ar = static_cast<float>(d.a);
+  const int dot = d.xpay ? d.dot : DOT_NONE;
+  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt), d.enc_set_rt};
+  const int* sel = d.rhs_map ? d.rhs_map : d.active;
+  if (d.dagger) {
+    if (d.xpay) launch_rloop_dot<true, true, BASIS>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<true, false, BASIS>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+  } else {
+    if (d.xpay) launch_rloop_dot<false, true, BASIS>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<false, false, BASIS>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+  }
+}
+
 // Threads carry 1 to 4 RHS slots (a slot past the last RHS reads zeros and
 // its arithmetic is wasted, so one RHS runs in a one-slot thread).  8-real
 // links are built for one and two slots only (their rebuild is long; wider
@@ -1133,6 +1638,12 @@ static bool lds_usable(const wd_gauge* gg, wd_prec prec, const LaunchCfg& c) {
 
 template <class S, int BASIS>
 static void launch_cfg(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
+  if constexpr (S::prec == WD_HALF_F16) {
+    if (c.rloop && gg->recon == 12) {
+      launch_rloop<BASIS>(gg, d, c, s);
+      return;
+    }
+  }
   if (gg->recon == 8) {
     if (c.nr == 1) launch_nr<S, 1, 8, false, BASIS>(gg, d, c, s);
     else launch_nr<S, 2, 8, false, BASIS>(gg, d, c, s);

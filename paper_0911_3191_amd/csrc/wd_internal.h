@@ -119,6 +119,7 @@ struct LaunchCfg {
   int out_nt = 0;   // output stores marked streaming
   int wgs = 0;      // cap on workgroups per CU (0: registers decide)
   int lds = 0;      // 16-bit formats: stage x/y neighbours in LDS
+  int rloop = 0;    // binary16, 12-real links: one thread per site loops over every RHS
 };
 void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c,
                        hipStream_t s);

@@ -1,7 +1,8 @@
 // Autotuner for the dslash launch shape: right-hand sides per thread (nr),
 // y-sub-slabs of an XCD's sweep (nsub, shortens the reuse distance of the
-// t-neighbours) and, for the 16-bit formats, LDS staging of the x/y
-// neighbours (lds).  (link_nt, a cache hint for link loads, is still parsed
+// t-neighbours), for the 16-bit formats LDS staging of the x/y neighbours
+// (lds), and for binary16 with 12-real links one thread per site looping
+// over every right-hand side (rloop).  (link_nt, a cache hint for link loads, is still parsed
 // but the kernels no longer use it and it is not searched.)
 //
 // The first eager launch for a (lattice, precision, nrhs) times each
@@ -11,9 +12,9 @@
 // output aliases their xpay source, use the default shape instead and do not
 // tune.  WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices
 // across processes (one "Lx Ly Lz Lt prec nrhs flags nr block gslow nsub
-// link_nt lds" line per entry, flags = 1 for 8-real links + 2 for temporal
+// link_nt lds rloop" line per entry, flags = 1 for 8-real links + 2 for temporal
 // gauge + 4 for UKQCD-basis fields); WD_TUNE_VERBOSE=1 prints every timed candidate to stderr;
-// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs[,lds]]]]" forces a shape
+// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs[,lds[,rloop]]]]]" forces a shape
 // (the RHS-group-slowest order, streaming output stores and the occupancy
 // cap are not searched: none paid on the lattices measured).
 #include <hip/hip_runtime.h>
@@ -57,13 +58,14 @@ void load_cache_locked() {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  int lx, ly, lz, lt, prec, nrhs, flags, nr, block, gslow, nsub, nt, lds;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &flags, &nr,
-                     &block, &gslow, &nsub, &nt, &lds) == 13) {
+  int lx, ly, lz, lt, prec, nrhs, flags, nr, block, gslow, nsub, nt, lds, rloop;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d", &lx, &ly, &lz, &lt, &prec, &nrhs, &flags, &nr,
+                     &block, &gslow, &nsub, &nt, &lds, &rloop) == 14) {
     if (nr >= 1 && nr <= 4 && block == 256 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
-        (nt == 0 || nt == 1) && (lds == 0 || lds == 1)) {
+        (nt == 0 || nt == 1) && (lds == 0 || lds == 1) && (rloop == 0 || rloop == 1)) {
       LaunchCfg c{nr, block, gslow, nsub, nt};
       c.lds = lds;
+      c.rloop = rloop;
       g_cache[Key{lx, ly, lz, lt * 8 + prec, nrhs, flags}] = c;
     }
   }
@@ -75,9 +77,9 @@ void save_entry_locked(const Key& k, const LaunchCfg& c) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
                std::get<3>(k) / 8, std::get<3>(k) % 8, std::get<4>(k), std::get<5>(k), c.nr, c.block, c.gslow,
-               c.nsub, c.link_nt, c.lds);
+               c.nsub, c.link_nt, c.lds, c.rloop);
   std::fclose(f);
 }
 
@@ -154,6 +156,24 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
       }
     }
   }
+  // binary16 with 12-real links: one thread per site over every RHS
+  if (prec == WD_HALF_F16 && g->recon == 12 && d.out.nrhs >= 2) {
+    for (int nsub = 1; nsub <= (slab ? 8 : 1); nsub *= 2) {
+      if (g->geom.L[1] % nsub) continue;
+      LaunchCfg c{1, 256, 0, nsub, 0};
+      c.rloop = 1;
+      float ms = time_cfg(g, prec, plain, c, s);
+      const float ms2 = time_cfg(g, prec, plain, c, s);
+      if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
+      if (verbose())
+        std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: rhs loop nsub %d -> %.1f us\n", g->geom.L[0],
+                     g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs, nsub, ms * 1e3f);
+      if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
   return best;
 }
 
@@ -163,11 +183,12 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
   const int nrhs = d.out.nrhs;
   // WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt]" forces one shape (tests sweep them with it)
   if (const char* f = std::getenv("WD_DSLASH_SHAPE")) {
-    int nr = 1, gslow = 0, nsub = 1, nt = 0, ont = 0, wgs = 0, lds = 0;
-    const int n = std::sscanf(f, "%d,%d,%d,%d,%d,%d,%d", &nr, &gslow, &nsub, &nt, &ont, &wgs, &lds);
+    int nr = 1, gslow = 0, nsub = 1, nt = 0, ont = 0, wgs = 0, lds = 0, rloop = 0;
+    const int n = std::sscanf(f, "%d,%d,%d,%d,%d,%d,%d,%d", &nr, &gslow, &nsub, &nt, &ont, &wgs, &lds, &rloop);
     if (n >= 3 && nr >= 1 && nr <= 4 && (gslow == 0 || gslow == 1) && nsub >= 1 && nsub <= 8 &&
-        (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8 && (lds == 0 || lds == 1))
-      return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs, lds};
+        (nt == 0 || nt == 1) && (ont == 0 || ont == 1) && wgs >= 0 && wgs <= 8 && (lds == 0 || lds == 1) &&
+        (rloop == 0 || rloop == 1))
+      return LaunchCfg{nr, 256, gslow, nsub, nt, ont, wgs, lds, rloop};
   }
   const Key k = key_of(g, prec, nrhs, d.basis);
   {

@@ -141,8 +141,14 @@ def test_ukqcd_every_launch_shape_and_rhs_count(prec, dims, monkeypatch):
                 monkeypatch.setenv("WD_DSLASH_SHAPE", f"{nr},0,{nsub},0,0,0,{lds}")
                 fout = s.field(prec, 5)
                 wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
-                results[(nr, nsub, lds)] = s.decode(prec, fout, 5)
-    ref = results[(2, 1, 0)]
+                results[(nr, nsub, lds, 0)] = s.decode(prec, fout, 5)
+    if prec == "f16":  # one thread per site over every RHS
+        for nsub in (1, 2):
+            monkeypatch.setenv("WD_DSLASH_SHAPE", f"1,0,{nsub},0,0,0,0,1")
+            fout = s.field(prec, 5)
+            wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
+            results[(1, nsub, 0, 1)] = s.decode(prec, fout, 5)
+    ref = results[(2, 1, 0, 0)]
     for key, val in results.items():
         assert np.array_equal(val, ref), key
     monkeypatch.delenv("WD_DSLASH_SHAPE")
@@ -157,10 +163,16 @@ def test_ukqcd_every_launch_shape_and_rhs_count(prec, dims, monkeypatch):
 
 @pytest.mark.parametrize("kind", ["i16", "f16"])
 @pytest.mark.parametrize("dagger", [0, 1])
-def test_ukqcd_16bit_dslash_on_quantised_inputs(kind, dagger):
+@pytest.mark.parametrize("sparse", [False, True])
+def test_ukqcd_16bit_dslash_on_quantised_inputs(kind, dagger, sparse):
     """The oracle fed the 16-bit links and the UKQCD-basis spinor quantised as
-    the kernel stores it: what remains is FP32 arithmetic and one output
-    rounding, bounded per site by the output norm."""
+    the kernel stores it.  int16: what remains is FP32 arithmetic and one
+    output rounding, bounded per site by the output norm.  binary16 also
+    rounds the projected half spinor and the rebuilt third link row once
+    each; with `sparse` (stored lower spins and colour 2 zero) both are exact
+    for output colours 0 and 1, which keep the int16 bound, otherwise eight
+    hops of half-spinor rounding (2^-10 of the neighbour norm each) are
+    allowed."""
     dims = (6, 4, 8, 10)
     U = wdinputs.gauge_random(dims, 0.5, 79)
     s = Setup(dims, U)
@@ -170,6 +182,11 @@ def test_ukqcd_16bit_dslash_on_quantised_inputs(kind, dagger):
     Uq[..., 2, :, 0], Uq[..., 2, :, 1] = c.real, c.imag
     psi = wdinputs.spinor_gaussian(dims, 80)
     _, po = oracle.split(dims, psi)
+    if sparse:
+        pu = to_uk(po)
+        pu[:, 2:, :, :] = 0.0
+        pu[:, :, 2, :] = 0.0
+        po = from_uk(pu)
     q, nm = oracle.encode_spinor16(kind, to_uk(po))
     po_q = from_uk(oracle.decode_spinor16(kind, q, nm))
     fin = s.encode_parity(kind, po, basis=UK)
@@ -180,6 +197,13 @@ def test_ukqcd_16bit_dslash_on_quantised_inputs(kind, dagger):
     site_norm = np.abs(ref).max(axis=1, keepdims=True)
     lsb = site_norm / 32767 if kind == "i16" else site_norm * 2.0 ** -11
     bound = 0.5 * lsb * 1.01 + 64 * 6e-8 * site_norm
+    if kind == "f16" and sparse:
+        keep = np.zeros((4, 3, 2), dtype=bool)
+        keep[:, :2, :] = True
+        got, ref = got[:, keep.reshape(-1)], ref[:, keep.reshape(-1)]
+        bound = np.broadcast_to(bound, got.shape)
+    elif kind == "f16":
+        bound = bound + 8 * 2 * 2.0 ** -10 * float(np.max(nm))
     ratio = np.abs(got - ref) / bound
     i, j = np.unravel_index(np.argmax(ratio), ratio.shape)
     assert ratio.max() <= 1.0, (f"site {i} comp {j}: got {got[i, j]!r} ref {ref[i, j]!r} "
@@ -193,3 +217,39 @@ def test_unknown_basis_is_rejected():
     with pytest.raises(wd.WDError) as e:
         wd.wd_dslash_field_basis(s.gauge, f, g, 0, 0, "fp32", 1, 2)
     assert e.value.status == wd.WD_EINVAL
+
+
+@pytest.mark.parametrize("basis", [0, UK], ids=["dr", "uk"])
+@pytest.mark.parametrize("tap", [True, False], ids=["antiperiodic", "periodic"])
+def test_rhs_loop_kernel_matches_slot_kernels_in_every_form(basis, tap, monkeypatch):
+    """The binary16 kernel in which one thread runs over every RHS must give
+    the slot kernels' bits for D and its adjoint, on both output parities, and
+    (DeGrand-Rossi fast path) for M_hat and its adjoint, which fuse the
+    x + a D y update into the second dslash."""
+    dims = (6, 4, 8, 6)
+    U = wdinputs.gauge_random(dims, 0.5, 81)
+    s = Setup(dims, U, tap=tap, precs=("f16",))
+    srcs = wdinputs.spinor_gaussian(dims, 82, nrhs=5)
+    pe = np.stack([oracle.split(dims, srcs[k])[0] for k in range(5)])
+    fin = s.encode_parity("f16", pe, nrhs=5, basis=basis)
+
+    def run(shape):
+        monkeypatch.setenv("WD_DSLASH_SHAPE", shape)
+        out = {}
+        for par in (0, 1):
+            for dag in (0, 1):
+                fo = s.field("f16", 5)
+                wd.wd_dslash_field_basis(s.gauge, fo, fin, par, dag, "f16", 5, basis)
+                out[("D", par, dag)] = s.decode("f16", fo, 5, basis=basis)
+        if basis == 0:
+            for dag in (0, 1):
+                fo, ft = s.field("f16", 5), s.field("f16", 5)
+                wd.wd_mat_pc_field(s.gauge, 0.124, fo, fin, ft, dag, "f16", 5)
+                out[("M", 0, dag)] = s.decode("f16", fo, 5)
+        return out
+
+    ref = run("2,0,1,0,0,0,0,0")
+    for nsub in (1, 2):
+        got = run(f"1,0,{nsub},0,0,0,0,1")
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (nsub, key)

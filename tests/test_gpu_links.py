@@ -55,7 +55,12 @@ def test_recon8_dslash_matches_oracle(dims, prec, dagger):
         q, nm = oracle.encode_spinor16(prec, po)
         ref_q = oracle.dslash_parity(dims, quantised_links8(prec, U), oracle.decode_spinor16(prec, q, nm), 0,
                                      dagger=bool(dagger))
-        assert rel_l2(got, ref_q) <= 2e-4
+        # int16 adds FP32 arithmetic and one output rounding.  binary16
+        # multiplies binary16 operands: the rebuilt link and the projected
+        # half spinor are rounded once more each (2^-11 relative at most, rms
+        # 2^-11/sqrt(3)); with the output rounding that is rms about 2^-11,
+        # held to twice that.
+        assert rel_l2(got, ref_q) <= (2e-4 if prec == "i16" else 2.0 ** -10)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "f16"])
