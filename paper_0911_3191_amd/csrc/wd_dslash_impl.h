@@ -756,15 +756,12 @@ struct LdsCtx {
   int yl;               // this thread's y within its sub-slab
 };
 
-template <class S, int NR>
-__device__ __forceinline__ void lds_stage(const DslashGeom& g, int xcd, int site_block, const SpinorBuf<S> (&in)[NR],
-                                          const bool (&on)[NR], uint4* chunks, float* norms, int* rowbase,
-                                          int* base_out) {
+// Row table of the staged window: checkerboard index of each staged row's
+// first site (-1: outside the slab, never read); returns the first staged row.
+__device__ __forceinline__ int lds_rows(const DslashGeom& g, int xcd, int site_block, int* rowbase) {
   const int first = (int)fdiv((uint32_t)(site_block * blockDim.x), g.div_lxh);
   const int base = first - 1;
-  *base_out = base;
-  const int n = g.lds_cap;
-  const int nrows = n / g.Lxh;
+  const int nrows = g.lds_cap / g.Lxh;
   // checkerboard index of each staged row's first site (-1: outside the slab, never read)
   for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
     const int rs = base + r;
@@ -782,7 +779,15 @@ __device__ __forceinline__ void lds_stage(const DslashGeom& g, int xcd, int site
     }
     rowbase[r] = cb0;
   }
-  __syncthreads();
+  return base;
+}
+
+// Copies the staged rows of every active RHS slot into LDS (the row table
+// must be visible to every thread).
+template <class S, int NR>
+__device__ __forceinline__ void lds_copy(const DslashGeom& g, const SpinorBuf<S> (&in)[NR], const bool (&on)[NR],
+                                         uint4* chunks, float* norms, const int* rowbase) {
+  const int n = g.lds_cap;
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     if (!on[k]) continue;  // uniform across the block
@@ -798,6 +803,15 @@ __device__ __forceinline__ void lds_stage(const DslashGeom& g, int xcd, int site
           __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(in[k].norms, cbi * 4u, 0, 0));
     }
   }
+}
+
+template <class S, int NR>
+__device__ __forceinline__ void lds_stage(const DslashGeom& g, int xcd, int site_block, const SpinorBuf<S> (&in)[NR],
+                                          const bool (&on)[NR], uint4* chunks, float* norms, int* rowbase,
+                                          int* base_out) {
+  *base_out = lds_rows(g, xcd, site_block, rowbase);
+  __syncthreads();
+  lds_copy<S, NR>(g, in, on, chunks, norms, rowbase);
 }
 
 template <class S>
@@ -1324,9 +1338,11 @@ __device__ __forceinline__ HopIdx hop_index(const DslashGeom& g, int xh, int row
 }
 
 // Both hops of direction MU for one right-hand side, links given.
-template <int MU, bool DAGGER, int BASIS>
+// With LDS, lf / lb >= 0 name the staged slots of the forward / backward
+// neighbour (x and in-plane y hops).
+template <int MU, bool DAGGER, int BASIS, bool LDS>
 __device__ __forceinline__ void hop_pair16(Spinor<float>& acc, const SpinorBuf<SF16>& ib, const HopIdx& h,
-                                           const Link16& Uf, const Link16& Ub) {
+                                           const Link16& Uf, const Link16& Ub, const LdsCtx& lc, int lf, int lb) {
   if constexpr (MU == 3 && BASIS == kBasisUK) {
     constexpr int BF = DAGGER ? 0 : 2, BB = DAGGER ? 2 : 0;
     uint32_t w[6];
@@ -1338,9 +1354,11 @@ __device__ __forceinline__ void hop_pair16(Spinor<float>& acc, const SpinorBuf<S
   } else {
     Raw16 psi;
     float sc;
-    gather_spinor16<SF16>(ib, h.nf, psi, sc);
+    if (LDS && lf >= 0) lds_gather16<SF16>(lc, 0, lf, psi, sc);
+    else gather_spinor16<SF16>(ib, h.nf, psi, sc);
     hop16d<MU, DAGGER ? +1 : -1, false, BASIS>(acc, psi, Uf, h.flip_f ? -sc : sc);
-    gather_spinor16<SF16>(ib, h.nb, psi, sc);
+    if (LDS && lb >= 0) lds_gather16<SF16>(lc, 0, lb, psi, sc);
+    else gather_spinor16<SF16>(ib, h.nb, psi, sc);
     hop16d<MU, DAGGER ? -1 : +1, true, BASIS>(acc, psi, Ub, h.flip_b ? -sc : sc);
   }
 }
@@ -1361,8 +1379,10 @@ __device__ __forceinline__ void link_pair16(const DslashGeom& g, const char* lin
 // workgroup are still in L2 when the next needs them, and each link is read
 // once per launch.  Sites map to workgroups as in dslash_kernel with a single
 // RHS group; the arithmetic per right-hand side is that of dslash_kernel, so
-// results are bitwise the same.
-template <bool DAGGER, bool XPAY, int DOT, int BASIS, class S2 = SF16>
+// results are bitwise the same.  With LDS (slab mapping only) the workgroup
+// stages each RHS's x/y neighbour rows in LDS before its hops, as lds_stage
+// does for the slot kernels.
+template <bool DAGGER, bool XPAY, int DOT, int BASIS, bool LDS, class S2 = SF16>
 __global__ void __launch_bounds__(kBlock) dslash16_rloop_kernel(DslashGeom g, const char* __restrict__ links,
                                                                FieldView out, FieldView in, FieldView xs,
                                                                FieldView ys, float a, int p,
@@ -1416,6 +1436,25 @@ __global__ void __launch_bounds__(kBlock) dslash16_rloop_kernel(DslashGeom g, co
   link_pair16<1>(g, links, p, cb, h1, Uf[1], Ub[1]);
   link_pair16<2>(g, links, p, cb, h2, Uf[2], Ub[2]);
   link_pair16<3>(g, links, p, cb, h3, Uf[3], Ub[3]);
+  LdsCtx lc{nullptr, nullptr, 0, 0, 0, 0};
+  [[maybe_unused]] uint4* lchunks = nullptr;
+  [[maybe_unused]] float* lnorms = nullptr;
+  [[maybe_unused]] int* rowbase = nullptr;
+  int lf0 = -1, lb0 = -1, lf1 = -1, lb1 = -1;
+  if constexpr (LDS) {
+    extern __shared__ uint4 lds_raw[];
+    lchunks = lds_raw;
+    lnorms = reinterpret_cast<float*>(lds_raw + 3 * g.lds_cap);
+    rowbase = reinterpret_cast<int*>(lnorms + g.lds_cap);
+    const int base = lds_rows(g, xcd, site_block, rowbase);  // read after the first barrier below
+    const int s_lds = valid ? site_block * (int)blockDim.x + (int)threadIdx.x : (g.Vh >> 3) - 1;
+    lc = LdsCtx{lchunks, lnorms, g.lds_cap, base, (int)fdiv((uint32_t)s_lds, g.div_lxh), X1 - (X1 / g.suby) * g.suby};
+    const int r0 = (lc.row - lc.base) * g.Lxh;
+    lf0 = r0 + (h0.nf - g.Lxh * row);
+    lb0 = r0 + (h0.nb - g.Lxh * row);
+    if (lc.yl + 1 < g.suby) lf1 = (lc.row + 1 - lc.base) * g.Lxh + xh;
+    if (lc.yl > 0) lb1 = (lc.row - 1 - lc.base) * g.Lxh + xh;
+  }
   for (int slot = 0; slot < g.nrhs; ++slot) {
     int r;
     if (g.mapped) {
@@ -1425,18 +1464,25 @@ __global__ void __launch_bounds__(kBlock) dslash16_rloop_kernel(DslashGeom g, co
       if (sel && !sel[slot]) continue;  // uniform across the block
     }
     const SpinorBuf<SF16> ib = spinor_buf<SF16>(in, r);
+    if constexpr (LDS) {
+      __syncthreads();  // the row table is written; the previous RHS's staged rows are read
+      const SpinorBuf<SF16> sb1[1] = {ib};
+      const bool on1[1] = {true};
+      lds_copy<SF16, 1>(g, sb1, on1, lchunks, lnorms, rowbase);
+      __syncthreads();
+    }
     Spinor<float> acc[1];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[0].v[s][c] = {0.0f, 0.0f};
-    hop_pair16<0, DAGGER, BASIS>(acc[0], ib, h0, Uf[0], Ub[0]);
+    hop_pair16<0, DAGGER, BASIS, LDS>(acc[0], ib, h0, Uf[0], Ub[0], lc, lf0, lb0);
     hop_fence<float, 1>(acc);
-    hop_pair16<1, DAGGER, BASIS>(acc[0], ib, h1, Uf[1], Ub[1]);
+    hop_pair16<1, DAGGER, BASIS, LDS>(acc[0], ib, h1, Uf[1], Ub[1], lc, lf1, lb1);
     hop_fence<float, 1>(acc);
-    hop_pair16<2, DAGGER, BASIS>(acc[0], ib, h2, Uf[2], Ub[2]);
+    hop_pair16<2, DAGGER, BASIS, LDS>(acc[0], ib, h2, Uf[2], Ub[2], lc, -1, -1);
     hop_fence<float, 1>(acc);
-    hop_pair16<3, DAGGER, BASIS>(acc[0], ib, h3, Uf[3], Ub[3]);
+    hop_pair16<3, DAGGER, BASIS, LDS>(acc[0], ib, h3, Uf[3], Ub[3], lc, -1, -1);
     hop_fence<float, 1>(acc);
     finish_rhs<SF16, XPAY, DOT, S2>(g, acc[0], r, cb, valid, pid, out, xs, ys, a, partials, enc);
   }
@@ -1571,31 +1617,49 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
   }
 }
 
-template <bool DAGGER, bool XPAY, int BASIS>
-static void launch_rloop_dot(int dot, unsigned grid, hipStream_t s, const DslashGeom& g, const char* links,
-                             FieldView fo, FieldView fi, FieldView fx, FieldView fy, float a, int p,
+template <bool DAGGER, bool XPAY, int BASIS, bool LDS>
+static void launch_rloop_dot(int dot, unsigned grid, size_t lds, hipStream_t s, const DslashGeom& g,
+                             const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy, float a, int p,
                              const int* sel, double* partials, EncView enc) {
   if constexpr (BASIS == kBasisDR || !XPAY) {
-    dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+    dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
   } else {
     switch (dot) {
       case DOT_YO:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_YO, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_YO, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OX:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OX, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OX, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OO:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OO, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OO, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       default:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS><<<grid, kBlock, 0, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
     }
   }
 }
 
+template <int BASIS, bool LDS>
+static void launch_rloop_dag(const DslashArgs& d, unsigned grid, size_t lds, hipStream_t s, const DslashGeom& g,
+                             const char* links) {
+  FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
+  const float ar = static_cast<float>(d.a);
+  const int dot = d.xpay ? d.dot : DOT_NONE;
+  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt), d.enc_set_rt};
+  const int* sel = d.rhs_map ? d.rhs_map : d.active;
+  if (d.dagger) {
+    if (d.xpay) launch_rloop_dot<true, true, BASIS, LDS>(dot, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<true, false, BASIS, LDS>(DOT_NONE, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+  } else {
+    if (d.xpay) launch_rloop_dot<false, true, BASIS, LDS>(dot, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<false, false, BASIS, LDS>(DOT_NONE, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+  }
+}
+
 // The RHS-loop launch (binary16, 12-real links): one RHS group covering the
-// whole batch, so the grid is one workgroup per site block.
+// whole batch, so the grid is one workgroup per site block.  LDS staging when
+// asked for, on the slab mapping, if its rows fit 62 KiB.
 template <int BASIS>
 static void launch_rloop(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
   const int n = d.rhs_map ? d.n_map : d.out.nrhs;
@@ -1606,18 +1670,9 @@ static void launch_rloop(const wd_gauge* gg, const DslashArgs& d, const LaunchCf
   g.tgauge = gg->tgauge;
   const char* links = static_cast<const char*>(gg->link[WD_HALF_F16]);
   const unsigned grid = grid_blocks(g);
-  FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
-  const float ar = static_cast<float>(d.a);
-  const int dot = d.xpay ? d.dot : DOT_NONE;
-  const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt), d.enc_set_rt};
-  const int* sel = d.rhs_map ? d.rhs_map : d.active;
-  if (d.dagger) {
-    if (d.xpay) launch_rloop_dot<true, true, BASIS>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-    else launch_rloop_dot<true, false, BASIS>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-  } else {
-    if (d.xpay) launch_rloop_dot<false, true, BASIS>(dot, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-    else launch_rloop_dot<false, false, BASIS>(DOT_NONE, grid, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-  }
+  const size_t lds = lds_stage_bytes(g, 1);
+  if (cfg.lds && g.slab && lds <= 63488) launch_rloop_dag<BASIS, true>(d, grid, lds, s, g, links);
+  else launch_rloop_dag<BASIS, false>(d, grid, 0, s, g, links);
 }
 
 // Threads carry 1 to 4 RHS slots (a slot past the last RHS reads zeros and

@@ -160,17 +160,21 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
   if (prec == WD_HALF_F16 && g->recon == 12 && d.out.nrhs >= 2) {
     for (int nsub = 1; nsub <= (slab ? 8 : 1); nsub *= 2) {
       if (g->geom.L[1] % nsub) continue;
-      LaunchCfg c{1, 256, 0, nsub, 0};
-      c.rloop = 1;
-      float ms = time_cfg(g, prec, plain, c, s);
-      const float ms2 = time_cfg(g, prec, plain, c, s);
-      if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
-      if (verbose())
-        std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: rhs loop nsub %d -> %.1f us\n", g->geom.L[0],
-                     g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs, nsub, ms * 1e3f);
-      if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
-        best_ms = ms;
-        best = c;
+      for (int lds = 0; lds <= (slab ? 1 : 0); ++lds) {
+        LaunchCfg c{1, 256, 0, nsub, 0};
+        c.rloop = 1;
+        c.lds = lds;
+        float ms = time_cfg(g, prec, plain, c, s);
+        const float ms2 = time_cfg(g, prec, plain, c, s);
+        if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
+        if (verbose())
+          std::fprintf(stderr, "[wd tune] %dx%dx%dx%d prec %d nrhs %d: rhs loop nsub %d lds %d -> %.1f us\n",
+                       g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, d.out.nrhs, nsub, lds,
+                       ms * 1e3f);
+        if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+          best_ms = ms;
+          best = c;
+        }
       }
     }
   }

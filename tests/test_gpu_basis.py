@@ -144,10 +144,11 @@ def test_ukqcd_every_launch_shape_and_rhs_count(prec, dims, monkeypatch):
                 results[(nr, nsub, lds, 0)] = s.decode(prec, fout, 5)
     if prec == "f16":  # one thread per site over every RHS
         for nsub in (1, 2):
-            monkeypatch.setenv("WD_DSLASH_SHAPE", f"1,0,{nsub},0,0,0,0,1")
-            fout = s.field(prec, 5)
-            wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
-            results[(1, nsub, 0, 1)] = s.decode(prec, fout, 5)
+            for lds in (0, 1):
+                monkeypatch.setenv("WD_DSLASH_SHAPE", f"1,0,{nsub},0,0,0,{lds},1")
+                fout = s.field(prec, 5)
+                wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 1, prec, 5, UK)
+                results[(1, nsub, lds, 1)] = s.decode(prec, fout, 5)
     ref = results[(2, 1, 0, 0)]
     for key, val in results.items():
         assert np.array_equal(val, ref), key
@@ -250,6 +251,7 @@ def test_rhs_loop_kernel_matches_slot_kernels_in_every_form(basis, tap, monkeypa
 
     ref = run("2,0,1,0,0,0,0,0")
     for nsub in (1, 2):
-        got = run(f"1,0,{nsub},0,0,0,0,1")
-        for key in ref:
-            assert np.array_equal(got[key], ref[key]), (nsub, key)
+        for lds in (0, 1):
+            got = run(f"1,0,{nsub},0,0,0,{lds},1")
+            for key in ref:
+                assert np.array_equal(got[key], ref[key]), (nsub, lds, key)

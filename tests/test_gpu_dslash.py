@@ -118,10 +118,11 @@ def test_every_launch_shape_gives_identical_results(prec, dims, monkeypatch):
                     results[(nr, gslow, nsub, lds, 0)] = s.decode(prec, fout, 3)
     if prec == "f16":  # one thread per site over every RHS
         for nsub in (1, 2, 3):
-            monkeypatch.setenv("WD_DSLASH_SHAPE", f"1,0,{nsub},0,0,0,0,1")
-            fout = s.field(prec, 3)
-            wd.wd_dslash_field(s.gauge, fout, fin, 0, 1, prec, 3)
-            results[(1, 0, nsub, 0, 1)] = s.decode(prec, fout, 3)
+            for lds in (0, 1):
+                monkeypatch.setenv("WD_DSLASH_SHAPE", f"1,0,{nsub},0,0,0,{lds},1")
+                fout = s.field(prec, 3)
+                wd.wd_dslash_field(s.gauge, fout, fin, 0, 1, prec, 3)
+                results[(1, 0, nsub, lds, 1)] = s.decode(prec, fout, 3)
     ref = results[(1, 0, 1, 0, 0)]
     for key, val in results.items():
         assert np.array_equal(val, ref), key

@@ -145,13 +145,15 @@ def test_check_every_out_of_range_is_refused():
         wd.bicgstab_solve(s.gauge, 0.12, x, bt, wd.solve_params(tol=1e-10, check_every=65), ws)
 
 
-@pytest.mark.parametrize("shape", ["3,0,2,1,0,0,0", "4,1,2,0,0,0,0", "1,1,2,0,0,0,1", "1,0,2,0,0,0,0,1"])
+@pytest.mark.parametrize("shape", ["3,0,2,1,0,0,0", "4,1,2,0,0,0,0", "1,1,2,0,0,0,1", "1,0,2,0,0,0,0,1",
+                                   "1,0,2,0,0,0,1,1"])
 def test_batch_under_any_launch_shape_equals_each_rhs_alone(shape, monkeypatch):
     """Launches with a fused dot product keep one sub-slab, so their partial
     records cover the same sites whatever else the shape says (RHS per thread,
     group order, link cache policy, LDS staging): a batch solved under a forced
     shape matches each RHS solved alone, bit for bit (the last shape is the
-    binary16 kernel in which one thread loops over every RHS of the batch)."""
+    binary16 kernel in which one thread loops over every RHS of the batch,
+    without and with LDS staging)."""
     dims, kappa = (8, 4, 8, 6), 0.124
     U = wdinputs.gauge_random(dims, 0.4, 15)
     s = Setup(dims, U)

@@ -42,16 +42,16 @@ def test_first_launch_tunes_once_and_records_its_choice(tmp_path, monkeypatch, c
     first = run()
     timed = [l for l in capfd.readouterr().err.splitlines() if l.startswith("[wd tune] 6x10x16x4 prec 3 nrhs 3:")]
     # candidates: 1-3 RHS slots x 1 or 2 y-sub-slabs (Ly = 10) x LDS staging off / on,
-    # and the one-thread-per-site RHS loop with 1 or 2 y-sub-slabs
-    assert len(timed) == 14, timed
-    assert sum("rhs loop" in t for t in timed) == 2, timed
+    # and the one-thread-per-site RHS loop with 1 or 2 y-sub-slabs x LDS staging off / on
+    assert len(timed) == 16, timed
+    assert sum("rhs loop" in t for t in timed) == 4, timed
     lines = _cache_lines(cache)
     assert len(lines) == 1, lines
     v = [int(t) for t in lines[0].split()]
     assert v[:7] == [6, 10, 16, 4, 3, 3, 4]  # dims, binary16, 3 RHS, UKQCD basis with 12-real links
     nr, block, gslow, nsub, link_nt, lds, rloop = v[7:]
     assert 1 <= nr <= 3 and block == 256 and gslow == 0 and nsub in (1, 2) and link_nt == 0 and lds in (0, 1)
-    assert rloop in (0, 1) and not (rloop and (nr != 1 or lds))
+    assert rloop in (0, 1) and not (rloop and nr != 1)
 
     # the choice is reused: nothing timed, nothing appended, the same bits
     second = run()
