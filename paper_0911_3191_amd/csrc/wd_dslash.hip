@@ -36,9 +36,13 @@ hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d
     return hipErrorInvalidValue;
   LaunchCfg c = tuned_dslash_config(g, prec, d, s);
   // A fused dot sums each workgroup's sites into one partial record; with one
-  // sub-slab those site sets are fixed whatever nr and gslow are, so the
-  // reduction -- and the solver -- give the same bits for every tuned shape.
-  if (d.xpay && d.dot != DOT_NONE) c.nsub = 1;
+  // sub-slab and 256-thread workgroups those site sets are fixed whatever the
+  // other fields are, so the reduction -- and the solver -- give the same bits
+  // for every tuned shape.
+  if (d.xpay && d.dot != DOT_NONE) {
+    c.nsub = 1;
+    c.block = 256;
+  }
   launch_dslash_cfg(g, prec, d, c, s);
   return hipGetLastError();
 }

@@ -1383,7 +1383,7 @@ __device__ __forceinline__ void link_pair16(const DslashGeom& g, const char* lin
 // stages each RHS's x/y neighbour rows in LDS before its hops, as lds_stage
 // does for the slot kernels.
 template <bool DAGGER, bool XPAY, int DOT, int BASIS, bool LDS, class S2 = SF16>
-__global__ void __launch_bounds__(kBlock) dslash16_rloop_kernel(DslashGeom g, const char* __restrict__ links,
+__global__ void __launch_bounds__(512) dslash16_rloop_kernel(DslashGeom g, const char* __restrict__ links,
                                                                FieldView out, FieldView in, FieldView xs,
                                                                FieldView ys, float a, int p,
                                                                const int* __restrict__ sel,
@@ -1596,6 +1596,7 @@ template <class S, int NR, int RECON, bool LDS, int BASIS>
 static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
   LaunchCfg c = cfg;
   c.nr = NR;  // the RHS slots of the kernel actually launched
+  if (c.block != 128) c.block = 256;  // the slot kernels are built for at most 256 threads
   DslashGeom g = make_dgeom(gg->geom, d.rhs_map ? d.n_map : d.out.nrhs, c);
   g.mapped = d.rhs_map ? 1 : 0;
   g.tgauge = gg->tgauge;
@@ -1618,61 +1619,68 @@ static void launch_nr(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& 
 }
 
 template <bool DAGGER, bool XPAY, int BASIS, bool LDS>
-static void launch_rloop_dot(int dot, unsigned grid, size_t lds, hipStream_t s, const DslashGeom& g,
+static void launch_rloop_dot(int dot, unsigned grid, int block, size_t lds, hipStream_t s, const DslashGeom& g,
                              const char* links, FieldView fo, FieldView fi, FieldView fx, FieldView fy, float a, int p,
                              const int* sel, double* partials, EncView enc) {
   if constexpr (BASIS == kBasisDR || !XPAY) {
-    dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+    dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
   } else {
     switch (dot) {
       case DOT_YO:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_YO, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_YO, BASIS, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OX:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OX, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OX, BASIS, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       case DOT_OO:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OO, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_OO, BASIS, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
         break;
       default:
-        dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, kBlock, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+        dslash16_rloop_kernel<DAGGER, XPAY, DOT_NONE, BASIS, LDS><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
     }
   }
 }
 
 template <int BASIS, bool LDS>
-static void launch_rloop_dag(const DslashArgs& d, unsigned grid, size_t lds, hipStream_t s, const DslashGeom& g,
-                             const char* links) {
+static void launch_rloop_dag(const DslashArgs& d, unsigned grid, int block, size_t lds, hipStream_t s,
+                             const DslashGeom& g, const char* links) {
   FieldView fo = fview(d.out), fi = fview(d.in), fx = fview(d.xpay), fy = fview(d.y);
   const float ar = static_cast<float>(d.a);
   const int dot = d.xpay ? d.dot : DOT_NONE;
   const EncView ev{fview(d.enc_rh), fview(d.enc_xh), fview(d.enc_rt), d.enc_set_rt};
   const int* sel = d.rhs_map ? d.rhs_map : d.active;
   if (d.dagger) {
-    if (d.xpay) launch_rloop_dot<true, true, BASIS, LDS>(dot, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-    else launch_rloop_dot<true, false, BASIS, LDS>(DOT_NONE, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    if (d.xpay) launch_rloop_dot<true, true, BASIS, LDS>(dot, grid, block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<true, false, BASIS, LDS>(DOT_NONE, grid, block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
   } else {
-    if (d.xpay) launch_rloop_dot<false, true, BASIS, LDS>(dot, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
-    else launch_rloop_dot<false, false, BASIS, LDS>(DOT_NONE, grid, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    if (d.xpay) launch_rloop_dot<false, true, BASIS, LDS>(dot, grid, block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
+    else launch_rloop_dot<false, false, BASIS, LDS>(DOT_NONE, grid, block, lds, s, g, links, fo, fi, fx, fy, ar, d.out_parity, sel, d.partials, ev);
   }
 }
 
 // The RHS-loop launch (binary16, 12-real links): one RHS group covering the
 // whole batch, so the grid is one workgroup per site block.  LDS staging when
-// asked for, on the slab mapping, if its rows fit 62 KiB.
+// asked for, on the slab mapping, if its rows fit 62 KiB.  Workgroups of
+// 128, 256 or 512 threads; a fused dot needs 256 (its block reduction sums
+// four waves).
 template <int BASIS>
 static void launch_rloop(const wd_gauge* gg, const DslashArgs& d, const LaunchCfg& cfg, hipStream_t s) {
   const int n = d.rhs_map ? d.n_map : d.out.nrhs;
   LaunchCfg c = cfg;
   c.nr = n;  // a single RHS group
+  if (c.block != 128 && c.block != 512) c.block = 256;
+  if (d.xpay && d.dot != DOT_NONE) c.block = 256;
   DslashGeom g = make_dgeom(gg->geom, n, c);
   g.mapped = d.rhs_map ? 1 : 0;
   g.tgauge = gg->tgauge;
   const char* links = static_cast<const char*>(gg->link[WD_HALF_F16]);
   const unsigned grid = grid_blocks(g);
-  const size_t lds = lds_stage_bytes(g, 1);
-  if (cfg.lds && g.slab && lds <= 63488) launch_rloop_dag<BASIS, true>(d, grid, lds, s, g, links);
-  else launch_rloop_dag<BASIS, false>(d, grid, 0, s, g, links);
+  const size_t stage = lds_stage_bytes(g, 1);
+  const size_t cap = lds_for(c.wgs);
+  if (cfg.lds && g.slab && stage <= 63488)
+    launch_rloop_dag<BASIS, true>(d, grid, c.block, std::max(stage, cap), s, g, links);
+  else
+    launch_rloop_dag<BASIS, false>(d, grid, c.block, cap, s, g, links);
 }
 
 // Threads carry 1 to 4 RHS slots (a slot past the last RHS reads zeros and

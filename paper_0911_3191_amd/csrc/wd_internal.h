@@ -126,11 +126,12 @@ void launch_dslash_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, con
 // Partial records per RHS written by a dslash launch with a fused dot.
 int dslash_partial_blocks(const Geom& geo, int nrhs, const LaunchCfg& c);
 // Autotuner (wd_tune.cpp): the configuration to use for this launch; times
-// the candidates on first use of (lattice, precision, nrhs) unless the
-// stream is being captured.
+// the candidates, in the launch's own form and on its own fields, on first
+// use of (lattice, precision, RHS count, link format and basis, form) unless
+// the stream is being captured.
 LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
-// Runs the tuner for (prec, nrhs) on the given fields (out = D in is computed).
-void tune_dslash(const wd_gauge* g, wd_prec prec, Field out, Field in, int basis, hipStream_t s);
+// Tunes the key of launch d now (the launch itself is not made).
+void tune_dslash(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStream_t s);
 
 // out_p = D_{p,1-p} in (dagger: adjoint).  When xpay_src is non-null:
 // out = xpay_src + a * D in (xpay_src has parity p, same precision).

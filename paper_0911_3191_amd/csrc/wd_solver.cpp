@@ -138,6 +138,44 @@ static hipError_t fin(wd_solver* h, int stage, const int* mask, bool after_dslas
     if (e_ != hipSuccess) return e_;         \
   } while (0)
 
+// Tunes the launch shapes of the inner-precision dslash forms of
+// iteration_body (each key once per process; see wd_tune.cpp).  Every
+// tuning launch reads zeros: p and v are zero after prepare, and the odd
+// temporary and t are zeroed here first, so the launches write zeros into
+// the odd temporary, v and t whichever keys are already cached (an
+// iteration writes those before it reads them, and reads v only times
+// beta = 0 in its first p-update, which a stale NaN would poison).
+static hipError_t pretune_inner(wd_solver* h) {
+  const wd_prec P = h->prm.inner;
+  WD_TRY(blas_zero(h->geom, P, h->to, nullptr, h->s));
+  WD_TRY(blas_zero(h->geom, P, h->t, nullptr, h->s));
+  auto form = [&](const Field& out, const Field& in, int parity, int dagger, const Field* xpay, int dot,
+                  const Field* y) {
+    DslashArgs d;
+    d.out = out;
+    d.in = in;
+    d.out_parity = parity;
+    d.dagger = dagger;
+    d.xpay = xpay;
+    d.a = -h->kappa * h->kappa;
+    d.dot = dot;
+    d.y = y;
+    d.partials = h->partials;
+    d.basis = kBasisUK;
+    tune_dslash(h->g, P, d, h->s);
+  };
+  form(h->to, h->p, 1, 0, nullptr, DOT_NONE, nullptr);  // first half of M_hat p
+  if (h->kind == WD_SOLVER_BICGSTAB) {
+    form(h->v, h->to, 0, 0, &h->p, DOT_YO, &h->rt);
+    form(h->t, h->to, 0, 0, &h->p, DOT_OX, nullptr);
+  } else {
+    form(h->t, h->to, 0, 0, &h->p, DOT_OO, nullptr);
+    form(h->to, h->t, 1, 1, nullptr, DOT_NONE, nullptr);
+    form(h->v, h->to, 0, 1, &h->t, DOT_NONE, nullptr);
+  }
+  return hipSuccess;  // a candidate that fails to launch is skipped by the tuner
+}
+
 // One Krylov iteration in the inner precision, all active RHS.
 static hipError_t iteration_body(wd_solver* h) {
   const Geom& g = h->geom;
@@ -432,9 +470,9 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
     return hip_fail(e, "pinned host buffer");
   }
   e = prepare(h);  // its FP64 dslash launches pick their own launch shape
-  // pick the inner-precision launch shape before any graph capture, on
-  // (p -> odd temporary); the temporary is scratch at this point
-  if (e == hipSuccess) tune_dslash(g, prm->inner, h->to, h->p, kBasisUK, h->s);
+  // pick the inner-precision launch shapes of every form an iteration uses
+  // before any graph capture
+  if (e == hipSuccess) e = pretune_inner(h);
   if (e == hipSuccess) e = read_flags(h);
   if (e != hipSuccess) {
     (void)hipHostFree(h->h_fl);
