@@ -46,11 +46,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wd_oracle.c")
 _LIB = os.path.join(_HERE, "libwdoracle.so")
+_LIB_SAN = os.path.join(_HERE, "libwdoracle_san.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math: IEEE semantics are relied on)."""
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math: IEEE semantics are relied on).
+    sanitize: libwdoracle_san.so, built with clang (the runtime of the
+    sanitized HIP library) under AddressSanitizer and UndefinedBehaviorSanitizer,
+    without OpenMP (its loops are correct serially); loaded when WD_ORACLE_LIB
+    names it."""
+    if sanitize:
+        clang = "/opt/rocm/llvm/bin/clang"
+        tmp = _LIB_SAN + ".tmp"
+        subprocess.check_call([clang, "-O1", "-g", "-shared", "-fPIC", "-std=c11", "-fno-fast-math",
+                               "-ffp-contract=off", "-fsanitize=address,undefined",
+                               "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                               "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_SAN)
+        return _LIB_SAN
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
@@ -63,9 +77,12 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("WD_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         i64p = ctypes.POINTER(ctypes.c_int64)

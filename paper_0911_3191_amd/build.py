@@ -3,6 +3,11 @@
 Every translation unit under csrc/ is compiled separately (in parallel) and
 linked into one shared library.  Packed FP32 instructions are disabled for
 all device code.
+
+`--sanitize` builds libwdslash_san.so instead, with the host code (API,
+validation, solver driver, tuner, scheduler) instrumented by AddressSanitizer
+and UndefinedBehaviorSanitizer; device code is built as usual.  It is loaded
+through WD_LIB_PATH with clang's ASan runtime preloaded (tests/sanitize.sh).
 """
 from __future__ import annotations
 
@@ -18,7 +23,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdslash.so")
+OBJ_SAN = os.path.join(HERE, "_build_san")
+LIB_SAN = os.path.join(HERE, "libwdslash_san.so")
 ARCH = "gfx950"
+# host-side sanitizers only: each -fsanitize= applies to the host pass
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
 
 
 def hipcc() -> str:
@@ -38,11 +48,12 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-ffp-contract=fast", "-munsafe-fp-atomics"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE, "-c", src, "-o", obj]
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(OBJ_SAN if sanitize else OBJ, os.path.basename(src) + ".o")
+    extra = SANITIZE if sanitize else []
+    cmd = [hipcc(), *COMMON, *DEVICE, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), *COMMON, "-x", "hip", *DEVICE, "-c", src, "-o", obj]
+        cmd = [hipcc(), *COMMON, "-x", "hip", *DEVICE, *extra, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{res.stdout}\n{res.stderr}")
@@ -53,23 +64,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libwdslash.so; returns the library path."""
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source and link libwdslash.so (libwdslash_san.so with
+    sanitize); returns the library path."""
+    obj_dir, lib = (OBJ_SAN, LIB_SAN) if sanitize else (OBJ, LIB)
+    os.makedirs(obj_dir, exist_ok=True)
     srcs = sources()
     workers = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(workers) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda src: _compile(src, sanitize), srcs))
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *(SANITIZE if sanitize else []), "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
