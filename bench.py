@@ -333,6 +333,198 @@ def oracle_checks(oracle, dims, U, x_host, x64_host, xtg_host, serve_kept, serve
     return out
 
 
+# ---- counter and trace summaries (no GPU: reads rocprofv3's CSV output) -------------
+DOT_NAMES = {0: "", 1: " <y,out>", 2: " <out,x>,|out|^2", 3: " |out|^2", 4: " res |r|^2", 5: " res->enc"}
+PREC_OF = {"SF64": "fp64", "SF32": "fp32", "SI16": "i16", "SF16": "f16"}
+
+
+def _csv_rows(root: str, suffix: str) -> list[dict]:
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _col(row: dict, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    raise KeyError(names)
+
+
+def dslash_launch(name: str, grid: int, block: int, Vh: int, slab: bool) -> dict | None:
+    """What a dslash dispatch computed, from its kernel template arguments and
+    launch size: precision, form, basis, kernel, RHS groups."""
+    if "dslash_kernel<" not in name and "dslash16_rloop_kernel<" not in name:
+        return None
+    a = name.index("<")
+    depth, b = 0, a
+    for b in range(a, len(name)):
+        depth += {"<": 1, ">": -1}.get(name[b], 0)
+        if depth == 0:
+            break
+    args = [t.strip().replace("wd::", "") for t in name[a + 1:b].split(",")]
+    if "rloop" in name:  # <DAGGER, XPAY, DOT, BASIS, LDS, S2>
+        prec, dag, xpay, dot, basis, lds, kind, nr = "f16", args[0], args[1], int(args[2]), int(args[3]), args[4], \
+            "rhs loop", 0
+    else:  # <S, DAGGER, XPAY, DOT, NR, RECON, LDS, BASIS, S2>
+        prec, dag, xpay, dot, nr = PREC_OF.get(args[0], args[0]), args[1], args[2], int(args[3]), int(args[4])
+        lds, basis, kind = args[6], int(args[7]), f"{nr} slot" + ("s" if nr > 1 else "")
+        if args[5] == "8":
+            kind += ", 8-real links"
+    per_group = (8 * -(-(Vh // 8) // block) if slab else -(-Vh // block)) * block
+    groups = grid // per_group if per_group else 0
+    form = ("D^dag" if dag == "true" else "D") if xpay == "false" else \
+        ("x + a D^dag" if dag == "true" else "x + a D") + DOT_NAMES.get(dot, f" dot {dot}")
+    return {"prec": prec, "form": form, "basis": "UKQCD" if basis == 1 else "DR", "kind": kind,
+            "lds": lds == "true", "block": block, "groups": groups,
+            "nrhs": (nr * groups) if nr else None, "xpay": xpay == "true", "dot": dot}
+
+
+def profile_summary(args) -> None:
+    """Print the counter/trace summary tables of the dslash launches found in a
+    directory of rocprofv3 CSV output (kernel trace + stats, FETCH_SIZE run,
+    WRITE_SIZE run), FETCH/WRITE scaled by the plain device copy of the same runs."""
+    import statistics
+    root = args.profile_summary
+    dims = tuple(int(v) for v in args.dims.split("x"))
+    Vh = int(np.prod(dims)) // 2
+    slab = dims[2] % 8 == 0
+    copy_bytes = int(max(args.copy_probe_gb, 4.0) * 1e9) // 8 * 8
+
+    def group_key(r):
+        name = _col(r, "Kernel_Name")
+        grid = int(_col(r, "Grid_Size", "Grid_Size_X"))
+        block = int(_col(r, "Workgroup_Size", "Workgroup_Size_X"))
+        return name, grid, block
+
+    # kernel trace: durations per (name, grid, block)
+    dur = {}
+    trace = sorted(_csv_rows(root, "kernel_trace.csv"), key=lambda r: int(r["Dispatch_Id"]))
+    for r in trace:
+        k = group_key(r)
+        dur.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    # counters: per dispatch value, per counter
+    cnt = {}
+    for r in _csv_rows(root, "counter_collection.csv"):
+        cnt.setdefault(_col(r, "Counter_Name"), {}).setdefault(group_key(r), []).append(float(r["Counter_Value"]))
+    scale = {}
+    for c, rows in cnt.items():  # the copy: the largest FETCH/WRITE among kernels named *copy*
+        cands = [max(v) for (n, _, _), v in rows.items() if "copy" in n.lower()]
+        if cands:
+            scale[c] = copy_bytes / (max(cands) * 1024.0)
+    keys = set(dur) | {k for rows in cnt.values() for k in rows}
+    table = []
+    for k in keys:
+        d = dslash_launch(k[0], k[1], k[2], Vh, slab)
+        if not d:
+            continue
+        f = cnt.get("FETCH_SIZE", {}).get(k)
+        w = cnt.get("WRITE_SIZE", {}).get(k)
+        t = dur.get(k)
+        if f or w:  # launch shapes of the run itself (tuning candidates carry no counters)
+            table.append((d, k, f, w, t))
+    # algorithmic reads of a launch: links once + per RHS the input spinor, the
+    # xpay source and y where the form reads them
+    def alg_reads(d):
+        n = d["nrhs"] or NRHS
+        per = SPINOR_B[d["prec"]] * (1 + d["xpay"] + (d["dot"] in (1, 4, 5)))
+        return Vh * (8 * LINK_B[d["prec"]] + n * per)
+
+    def label(d):
+        if d["form"] == "D" and d["basis"] == "UKQCD" and (d["nrhs"] in (1, NRHS) or d["kind"] == "rhs loop"):
+            return f"dslash_{d['prec']}_{d['nrhs'] or NRHS}rhs"
+        return ""
+
+    h = kernel_source_hash()
+    if args.profile_part == "trace":
+        print(f"Kernel source hash (wd_dslash_impl.h + wd_dslash.hip + wd_device.h + wd_reduce.h): `{h}`\n")
+        print(f"## Timed dslash launches (the last {args.dslash_reps} of each group: the back-to-back launches "
+              "bench.py times with HIP events)\n")
+        print("| label | kernel | form | grid | launches | mean us | median us | min us | max us | algorithmic GB/s |")
+        print("|---|---|---|---|---|---|---|---|---|---|")
+        for k, t in dur.items():
+            d = dslash_launch(k[0], k[1], k[2], Vh, slab)
+            if not d or not label(d) or k not in cnt.get("FETCH_SIZE", {}):
+                continue
+            last = t[-args.dslash_reps:]
+            m = statistics.mean(last)
+            gbs = dslash_bytes(d["prec"], d["nrhs"] or NRHS) * Vh / (m * 1e-6) / 1e9
+            kind = d["kind"] + (", LDS" if d["lds"] else "") + f", {d['block']} threads"
+            print(f"| {label(d)} | {d['prec']} {kind} | {d['form']} ({d['basis']}) | {k[1]} | {len(last)} | "
+                  f"{m:.1f} | {statistics.median(last):.1f} | {min(last):.1f} | {max(last):.1f} | {gbs:.0f} |")
+        stats = _csv_rows(root, "kernel_stats.csv")
+        tot = sum(float(r["TotalDurationNs"]) for r in stats)
+        print("\n## Kernels by total time in the run (all calls, every grid)\n")
+        print("| kernel | calls | total ms | share | mean us |")
+        print("|---|---|---|---|---|")
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+            name = r["Name"].split("(")[0].replace("void ", "").replace("wd::", "")
+            print(f"| `{name[:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.1f} | "
+                  f"{float(r['TotalDurationNs']) / tot:.3f} | {float(r['AverageNs']) * 1e-3:.1f} |")
+        return
+    if args.profile_part == "counters":
+        # every counter of the run, median per labelled dslash group, with derived rates
+        print(f"Kernel source hash (wd_dslash_impl.h + wd_dslash.hip + wd_device.h + wd_reduce.h): `{h}`\n")
+        names = sorted(cnt)
+        groups = []
+        for k in {k for rows in cnt.values() for k in rows}:
+            d = dslash_launch(k[0], k[1], k[2], Vh, slab)
+            if d and label(d):
+                groups.append((label(d), d, k))
+        print("| label | kernel | " + " | ".join(names) + " |")
+        print("|---|---|" + "---|" * len(names))
+        med = {}
+        for lab, d, k in sorted(groups):
+            med[lab] = {c: statistics.median(cnt[c][k]) for c in names if k in cnt[c]}
+            kind = d["kind"] + (", LDS" if d["lds"] else "") + f", {d['block']} threads"
+            print(f"| {lab} | {d['prec']} {kind} | " +
+                  " | ".join(f"{med[lab].get(c, float('nan')):.4g}" for c in names) + " |")
+        print("\nDerived (per launch; GRBM_GUI_ACTIVE counts the 8 XCDs):\n")
+        print("| label | VALU busy | TA busy avg / max | TCP pending-stall share | L1->L2 latency (clk) | "
+              "L2 hit rate | waves issuing nothing (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) |")
+        print("|---|---|---|---|---|---|---|")
+        for lab, m in med.items():
+            cyc = m.get("GRBM_GUI_ACTIVE", float("nan")) / 8  # clocks of one XCD
+            f = lambda v: f"{v:.2f}" if v == v else "-"
+            valu = m.get("SQ_INSTS_VALU", float("nan")) * 4 / 1024 / cyc
+            ta = (m.get("TA_BUSY_avr", float("nan")) / cyc, m.get("TA_BUSY_max", float("nan")) / cyc)
+            tcp = m.get("TCP_PENDING_STALL_CYCLES_sum", float("nan")) / 256 / cyc
+            lat = m.get("TCP_TCC_READ_REQ_LATENCY_sum", float("nan")) / m.get("TCP_TCC_READ_REQ_sum", float("nan"))
+            hit = m.get("TCC_HIT_sum", float("nan")) / (m.get("TCC_HIT_sum", float("nan"))
+                                                         + m.get("TCC_MISS_sum", float("nan")))
+            wait = m.get("SQ_WAIT_INST_ANY", float("nan")) / m.get("SQ_WAVE_CYCLES", float("nan"))
+            print(f"| {lab} | {f(valu)} | {f(ta[0])} / {f(ta[1])} | {f(tcp)} | {lat:.0f} | {f(hit)} | {f(wait)} |")
+        return
+    print(f"Counter scaling from the plain device copy of {copy_bytes / 1e9:.1f} GB in the same runs: "
+          + ", ".join(f"{c} x {v:.3f}" for c, v in sorted(scale.items())) + ".\n")
+    print("Per launch, median over the launches of each group.  `fetch`/`write` are bytes; "
+          "`ratio` = fetch / algorithmic reads; `us` = mean kernel-trace duration of the group "
+          f"(solver launches late in a solve skip converged RHS), `last {args.dslash_reps}` = mean of "
+          f"its last {args.dslash_reps} launches (for the labelled dslash rows: the bench's timed, "
+          "back-to-back launches).  A RHS-loop launch covers every RHS of its launch (12 here).\n")
+    print(f"| label | fetch | write | source hash | launches | us | last {args.dslash_reps} us | kernel | "
+          "form | RHS | algorithmic reads | ratio |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
+    order = sorted(table, key=lambda e: -(sum(e[4]) if e[4] else 0))
+    for d, k, f, w, t in order:
+        fb = statistics.median(f) * 1024 * scale.get("FETCH_SIZE", 1.0) if f else None
+        wb = statistics.median(w) * 1024 * scale.get("WRITE_SIZE", 1.0) if w else None
+        n = len(t) if t else (len(f) if f else 0)
+        alg = alg_reads(d)
+        kind = d["kind"] + (", LDS" if d["lds"] else "") + f", {d['block']} threads"
+        def e(v):
+            return f"{v:.4e}" if v is not None else "-"
+        us = f"{statistics.mean(t):.1f}" if t else "-"
+        last = f"{statistics.mean(t[-args.dslash_reps:]):.1f}" if t else "-"
+        ratio = f"{fb / alg:.2f}" if fb is not None else "-"
+        print(f"| {label(d)} | {e(fb)} | {e(wb)} | {h} | {n} | {us} | {last} | {d['prec']} {kind} | "
+              f"{d['form']} ({d['basis']}) | {d['nrhs'] or NRHS} | {alg:.4e} | {ratio} |")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +545,12 @@ def parse():
                     help="skip the oracle's true residuals of the GPU solutions")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter scaling)")
+    ap.add_argument("--profile-summary", metavar="DIR", default=None,
+                    help="print the dslash counter/trace tables of the rocprofv3 CSV output under DIR "
+                         "(kernel trace, FETCH_SIZE and WRITE_SIZE runs) and exit; no GPU")
+    ap.add_argument("--profile-part", choices=["traffic", "trace", "counters"], default="traffic",
+                    help="with --profile-summary: the FETCH/WRITE table, the kernel-trace tables, or the "
+                         "medians of every counter of the run")
     ap.add_argument("--rhs-scan", action="store_true",
                     help="also time the FP64 and inner-precision dslash against the number of RHS "
                          "per launch (1, 2, 3, 4, 6, 12)")
@@ -365,6 +563,9 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.profile_summary:
+        profile_summary(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no "
                                    "multi-GPU path (--gpus must be 1)", "n_gpus": args.gpus}))
@@ -690,11 +891,13 @@ def main():
                    "lattice": args.dims, "kappa": KAPPA, "eps": EPS, "seed": SEED, "nrhs": NRHS,
                    "sources": "12 spin-colour point sources at the origin", "inner": inner,
                    "delta": 0.1, "recon": 12, "graph": True, "spin_basis": "UKQCD (solver-internal)",
-                   "arith": "f32 inner, f64 reductions/updates"},
+                   "arith": (("inner dslash: binary16 projections and binary16 x binary16 products "
+                              "summed in f32 (v_dot2_f32_f16), f32 accumulation" if inner == "f16" else
+                              "inner: f32 arithmetic") + "; f64 reductions, reliable updates and solution")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": f"dslash_kernel<{inner}> {NRHS}-RHS, UKQCD basis",
+                     "kernel": f"{inner} dslash, {NRHS} RHS per launch at the tuned launch shape, UKQCD basis",
                      "bytes_per_launch": dbytes, "us_per_launch": round(t_dslash * 1e6, 1),
                      "flops_per_launch": dflops, "alu_achieved_TFLOPs": round(tflops, 2),
                      "alu_frac": round(tflops / ALU_PEAK_TFLOPS, 4),
