@@ -640,6 +640,10 @@ def main():
         pdc = wd.solve_params(tol=1e-12, maxiter=20000, inner=inner, delta=0.1, nrhs=NRHS, use_graph=True,
                               restart=True)
         xdc = torch.zeros_like(b)
+        # untimed first: tunes the subset launches of the update sizes this solve meets
+        with torch.cuda.stream(stream):
+            wd.bicgstab_solve(gauge, KAPPA, xdc, b, pdc, ws, stream)
+        xdc.zero_()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         with torch.cuda.stream(stream):
