@@ -805,6 +805,32 @@ __device__ __forceinline__ void lds_copy(const DslashGeom& g, const SpinorBuf<S>
   }
 }
 
+// Issues the copy of one RHS's staged rows straight into LDS (buffer loads
+// that write LDS, no registers: a wave's 64 lanes fill 64 consecutive 16-byte
+// or 4-byte slots from the wave-uniform base).  Returns at once; the data is
+// there after the issuing wave's vmcnt reaches 0, and for the other waves
+// after a barrier that follows that wait.  Rows outside the slab are skipped.
+__device__ __forceinline__ void lds_issue16(const DslashGeom& g, const SpinorBuf<SF16>& in, uint4* chunks,
+                                            float* norms, const int* rowbase) {
+  using lds_ptr = __attribute__((address_space(3))) void*;
+  const int n = g.lds_cap;
+  for (int i = 0; i * (int)blockDim.x < n; ++i) {
+    // first slot of this wave's 64 (uniform), and this lane's slot
+    const int base = __builtin_amdgcn_readfirstlane(i * (int)blockDim.x + ((int)threadIdx.x & ~63));
+    const int sl = i * (int)blockDim.x + (int)threadIdx.x;
+    if (sl >= n) continue;
+    const int rr = (int)fdiv((uint32_t)sl, g.div_lxh);
+    const int cb0 = rowbase[rr];
+    if (cb0 < 0) continue;
+    const uint32_t cbi = (uint32_t)(cb0 + sl - rr * g.Lxh);
+#pragma unroll
+    for (int part = 0; part < 3; ++part)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(in.chunks, (lds_ptr)(chunks + part * n + base), 16, cbi * 16u,
+                                               part * in.chunk_bytes, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(in.norms, (lds_ptr)(norms + base), 4, cbi * 4u, 0, 0, 0);
+  }
+}
+
 template <class S, int NR>
 __device__ __forceinline__ void lds_stage(const DslashGeom& g, int xcd, int site_block, const SpinorBuf<S> (&in)[NR],
                                           const bool (&on)[NR], uint4* chunks, float* norms, int* rowbase,
@@ -1380,8 +1406,10 @@ __device__ __forceinline__ void link_pair16(const DslashGeom& g, const char* lin
 // once per launch.  Sites map to workgroups as in dslash_kernel with a single
 // RHS group; the arithmetic per right-hand side is that of dslash_kernel, so
 // results are bitwise the same.  With LDS (slab mapping only) the workgroup
-// stages each RHS's x/y neighbour rows in LDS before its hops, as lds_stage
-// does for the slot kernels.
+// stages the x/y neighbour rows of each RHS in LDS (the rows of lds_stage),
+// double-buffered: the rows of the next RHS are loaded straight into the
+// other buffer while the current RHS computes, and one wait plus barrier per
+// RHS hands the buffers over.
 template <bool DAGGER, bool XPAY, int DOT, int BASIS, bool LDS, class S2 = SF16>
 __global__ void __launch_bounds__(512) dslash16_rloop_kernel(DslashGeom g, const char* __restrict__ links,
                                                                FieldView out, FieldView in, FieldView xs,
@@ -1437,16 +1465,16 @@ __global__ void __launch_bounds__(512) dslash16_rloop_kernel(DslashGeom g, const
   link_pair16<2>(g, links, p, cb, h2, Uf[2], Ub[2]);
   link_pair16<3>(g, links, p, cb, h3, Uf[3], Ub[3]);
   LdsCtx lc{nullptr, nullptr, 0, 0, 0, 0};
-  [[maybe_unused]] uint4* lchunks = nullptr;
-  [[maybe_unused]] float* lnorms = nullptr;
+  [[maybe_unused]] uint4* lchunks = nullptr;  // [buffer][3][cap]
+  [[maybe_unused]] float* lnorms = nullptr;   // [buffer][cap]
   [[maybe_unused]] int* rowbase = nullptr;
   int lf0 = -1, lb0 = -1, lf1 = -1, lb1 = -1;
   if constexpr (LDS) {
     extern __shared__ uint4 lds_raw[];
     lchunks = lds_raw;
-    lnorms = reinterpret_cast<float*>(lds_raw + 3 * g.lds_cap);
-    rowbase = reinterpret_cast<int*>(lnorms + g.lds_cap);
-    const int base = lds_rows(g, xcd, site_block, rowbase);  // read after the first barrier below
+    lnorms = reinterpret_cast<float*>(lds_raw + 6 * g.lds_cap);
+    rowbase = reinterpret_cast<int*>(lnorms + 2 * g.lds_cap);
+    const int base = lds_rows(g, xcd, site_block, rowbase);
     const int s_lds = valid ? site_block * (int)blockDim.x + (int)threadIdx.x : (g.Vh >> 3) - 1;
     lc = LdsCtx{lchunks, lnorms, g.lds_cap, base, (int)fdiv((uint32_t)s_lds, g.div_lxh), X1 - (X1 / g.suby) * g.suby};
     const int r0 = (lc.row - lc.base) * g.Lxh;
@@ -1455,21 +1483,33 @@ __global__ void __launch_bounds__(512) dslash16_rloop_kernel(DslashGeom g, const
     if (lc.yl + 1 < g.suby) lf1 = (lc.row + 1 - lc.base) * g.Lxh + xh;
     if (lc.yl > 0) lb1 = (lc.row - 1 - lc.base) * g.Lxh + xh;
   }
-  for (int slot = 0; slot < g.nrhs; ++slot) {
-    int r;
-    if (g.mapped) {
-      r = sel[slot];
-    } else {
-      r = slot;
-      if (sel && !sel[slot]) continue;  // uniform across the block
-    }
+  // RHS of batch slot k (with a map: the listed one) and the next slot from k
+  // on that is active; all uniform across the block
+  auto rhs_of = [&](int k) { return g.mapped ? sel[k] : k; };
+  auto next_active = [&](int k) {
+    if (!g.mapped && sel)
+      while (k < g.nrhs && !sel[k]) ++k;
+    return k;
+  };
+  int slot = next_active(0);
+  int buf = 0;
+  if constexpr (LDS) {
+    __syncthreads();  // the row table is written
+    if (slot < g.nrhs) lds_issue16(g, spinor_buf<SF16>(in, rhs_of(slot)), lchunks, lnorms, rowbase);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  while (slot < g.nrhs) {
+    const int r = rhs_of(slot);
+    const int nxt = next_active(slot + 1);
     const SpinorBuf<SF16> ib = spinor_buf<SF16>(in, r);
     if constexpr (LDS) {
-      __syncthreads();  // the row table is written; the previous RHS's staged rows are read
-      const SpinorBuf<SF16> sb1[1] = {ib};
-      const bool on1[1] = {true};
-      lds_copy<SF16, 1>(g, sb1, on1, lchunks, lnorms, rowbase);
-      __syncthreads();
+      // the next RHS's rows go into the other buffer while this one computes
+      if (nxt < g.nrhs)
+        lds_issue16(g, spinor_buf<SF16>(in, rhs_of(nxt)), lchunks + 3 * g.lds_cap * (buf ^ 1),
+                    lnorms + g.lds_cap * (buf ^ 1), rowbase);
+      lc.chunks = lchunks + 3 * g.lds_cap * buf;
+      lc.norms = lnorms + g.lds_cap * buf;
     }
     Spinor<float> acc[1];
 #pragma unroll
@@ -1485,6 +1525,14 @@ __global__ void __launch_bounds__(512) dslash16_rloop_kernel(DslashGeom g, const
     hop_pair16<3, DAGGER, BASIS, LDS>(acc[0], ib, h3, Uf[3], Ub[3], lc, -1, -1);
     hop_fence<float, 1>(acc);
     finish_rhs<SF16, XPAY, DOT, S2>(g, acc[0], r, cb, valid, pid, out, xs, ys, a, partials, enc);
+    if constexpr (LDS) {
+      // this wave's copies of the next RHS have landed and its reads of this
+      // buffer are done; after the barrier every wave's are
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    slot = nxt;
+    buf ^= 1;
   }
 }
 
@@ -1675,7 +1723,7 @@ static void launch_rloop(const wd_gauge* gg, const DslashArgs& d, const LaunchCf
   g.tgauge = gg->tgauge;
   const char* links = static_cast<const char*>(gg->link[WD_HALF_F16]);
   const unsigned grid = grid_blocks(g);
-  const size_t stage = lds_stage_bytes(g, 1);
+  const size_t stage = lds_stage_bytes(g, 2);  // two buffers of one RHS each
   const size_t cap = lds_for(c.wgs);
   if (cfg.lds && g.slab && stage <= 63488)
     launch_rloop_dag<BASIS, true>(d, grid, c.block, std::max(stage, cap), s, g, links);
