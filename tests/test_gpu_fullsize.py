@@ -48,23 +48,28 @@ def sample_sites(dims, n, seed):
 
 @pytest.fixture(scope="module")
 def big():
+    """(setup, full-lattice sources, sampled sites, oracle outputs per source,
+    canonical odd-parity sources)."""
     U = wdinputs.gauge_random(DIMS, 0.3, 5)
     s = Setup(DIMS, U)
     V = s.V
     cbs = sample_sites(DIMS, 4000, 9)
     src = torch.empty((NRHS, V, 4, 3, 2), dtype=torch.float64, device=DEV)
+    src_odd = torch.empty((NRHS, s.Vh, 4, 3, 2), dtype=torch.float64, device=DEV)  # canonical odd parity
     expect = np.empty((NSRC, len(cbs), 4, 3, 2))
     for j in range(NSRC):
         psi = wdinputs.spinor_gaussian(DIMS, 900 + j)
         _, odd = oracle.split(DIMS, psi)
         expect[j] = oracle.dslash_parity_sites(DIMS, U, odd, 0, cbs)
         dev = torch.from_numpy(psi.reshape(V, 4, 3, 2)).to(DEV)
+        dev_odd = torch.from_numpy(np.ascontiguousarray(odd)).to(DEV)
         for k in range(j, NRHS, NSRC):
             src[k] = dev * float(2 ** (k // NSRC))
-        del psi, odd, dev
+            src_odd[k] = dev_odd * float(2 ** (k // NSRC))
+        del psi, odd, dev, dev_odd
     torch.cuda.synchronize()
-    yield s, src, cbs, expect
-    del src
+    yield s, src, cbs, expect, src_odd
+    del src, src_odd
     torch.cuda.empty_cache()
 
 
@@ -83,7 +88,7 @@ def run(s, src, cbs, prec, nrhs):
 
 @pytest.mark.parametrize("prec", ["f16", "i16", "fp32"])
 def test_12rhs_launch_at_full_size(big, prec):
-    s, src, cbs, expect = big
+    s, src, cbs, expect, _ = big
     got = run(s, src, cbs, prec, NRHS)
     for k in range(NRHS):
         ref = expect[k % NSRC] * float(2 ** (k // NSRC))
@@ -93,7 +98,27 @@ def test_12rhs_launch_at_full_size(big, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "i16", "f16"])
 def test_single_rhs_launch_at_full_size(big, prec):
-    s, src, cbs, expect = big
+    s, src, cbs, expect, _ = big
     got = run(s, src, cbs, prec, 1)
     err = rel_l2(got[0], expect[0])
     assert err <= TOL[prec], f"{prec}: rel L2 {err:.3e} on {len(cbs)} sampled sites"
+
+
+@pytest.mark.parametrize("prec", ["f16", "i16", "fp32"])
+def test_12rhs_ukqcd_launch_at_full_size(big, prec):
+    """The launch the benchmark times: 12 RHS on UKQCD-basis fields at the tuned
+    shape (binary16: the RHS-loop kernel), canonical odd-parity sources
+    encoded into the basis, the output decoded back to DeGrand-Rossi."""
+    s, _, cbs, expect, src_odd = big
+    fin = wd.new_field(s.lat, prec, NRHS)
+    fout = wd.new_field(s.lat, prec, NRHS)
+    wd.wd_spinor_encode_basis(s.lat, prec, NRHS, wd.WD_BASIS_UKQCD, fin, src_odd)
+    wd.wd_dslash_field_basis(s.gauge, fout, fin, 0, 0, prec, NRHS, wd.WD_BASIS_UKQCD)
+    out = torch.empty((NRHS, s.Vh, 4, 3, 2), dtype=torch.float64, device=DEV)
+    wd.wd_spinor_decode_basis(s.lat, prec, NRHS, wd.WD_BASIS_UKQCD, out, fout)
+    got = out[:, torch.from_numpy(cbs).to(DEV)].cpu().numpy()
+    del fin, fout, out
+    for k in range(NRHS):
+        ref = expect[k % NSRC] * float(2 ** (k // NSRC))
+        err = rel_l2(got[k], ref)
+        assert err <= TOL[prec], f"{prec} rhs {k}: rel L2 {err:.3e} on {len(cbs)} sampled sites"
