@@ -26,7 +26,8 @@
 // size for the winner, then the occupancy cap for that; a subset launch
 // stops after the first stage with one sub-slab.  Launches made
 // while the stream is being captured into a graph, or whose output aliases
-// their xpay source, use the default shape and do not tune.
+// one of their inputs (xpay source, y, in), use the default shape and do not
+// tune.
 //
 // WD_TUNE=0 disables tuning; WD_TUNE_CACHE=<file> keeps the choices across
 // processes (one "Lx Ly Lz Lt prec nrhs flags form nr block gslow nsub
@@ -262,7 +263,9 @@ LaunchCfg tuned_dslash_config(const wd_gauge* g, wd_prec prec, const DslashArgs&
   if (!tuning_enabled() || d.no_tune) return default_cfg(nrhs);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return default_cfg(nrhs);
-  if (d.xpay && d.xpay->ptr == d.out.ptr) return default_cfg(nrhs);
+  // repeated launches must leave the result unchanged: no output may alias an input
+  if ((d.xpay && d.xpay->ptr == d.out.ptr) || (d.y && d.y->ptr == d.out.ptr) || d.in.ptr == d.out.ptr)
+    return default_cfg(nrhs);
   const LaunchCfg best = run_tuner(g, prec, d, s);
   std::lock_guard<std::mutex> lock(g_mu);
   g_cache[k] = best;
