@@ -48,6 +48,21 @@
  *   Every entry point validates its arguments before launching anything and
  *   returns a wd_status; no exception crosses the ABI.  wd_last_error() gives a
  *   thread-local message for the last failing call on the calling thread.
+ *
+ * Launch shapes (environment, read at run time)
+ *   The first eager dslash launch of each (lattice, precision, RHS count, link
+ *   format, spin basis, form) times candidate launch shapes on the caller's
+ *   stream and keeps the fastest; launches under graph capture use a default
+ *   shape.  Every shape gives the same bits.
+ *   WD_TUNE=0             no tuning (default shapes)
+ *   WD_TUNE_CACHE=<file>  keep the choices across processes (appended, one
+ *                         line per key)
+ *   WD_TUNE_VERBOSE=1     print every timed candidate to stderr
+ *   WD_DSLASH_SHAPE=...   force one shape:
+ *                         "nr,gslow,nsub[,link_nt[,out_nt[,wgs[,lds[,rloop[,block]]]]]]"
+ *                         (RHS slots per thread, RHS-group order, y-sub-slabs,
+ *                         cache hints, workgroups per CU cap, LDS staging,
+ *                         binary16 RHS loop, workgroup size)
  */
 #ifndef WD_H
 #define WD_H
