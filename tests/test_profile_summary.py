@@ -96,3 +96,26 @@ def test_trace_part_reports_the_timed_launches(runs):
     cells = [c.strip() for c in line.strip().strip("|").split("|")]
     assert cells[4] == "3" and float(cells[5]) == pytest.approx(53.0)
     assert "Kernels by total time" in text
+
+
+def test_bench_refuses_more_than_one_gpu():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True)
+    assert out.returncode == 2
+    line = out.stdout.strip().splitlines()[-1]
+    assert "exactly one GPU" in line and '"n_gpus": 2' in line
+
+
+def test_traffic_is_read_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    """bench's traffic lookup takes FETCH + WRITE of the labelled row, and
+    nothing when the table was taken on another kernel source."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "dslash_traffic_48x48x48x96.md").write_text(
+        "| dslash_f16_12rhs | 1.0000e+10 | 3.0000e+09 | 0000000000000000 | 5 | 1.0 | 1.0 | k | D | 12 | 4.0e9 | 2.5 |\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "1111111111111111")
+    assert bench.profiled_traffic("dslash_f16_12rhs", (48, 48, 48, 96)) is None  # another source
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.profiled_traffic("dslash_f16_12rhs", (48, 48, 48, 96)) == pytest.approx(1.3e10)
+    assert bench.profiled_traffic("dslash_fp64_1rhs", (48, 48, 48, 96)) is None  # no such row
