@@ -34,6 +34,9 @@ hipError_t launch_dslash_ex(const wd_gauge* g, wd_prec prec, const DslashArgs& d
       (prec != WD_FP64 || !d.xpay || !d.y || d.dagger || d.basis != kBasisUK || !d.enc_rh || !d.enc_xh ||
        !d.enc_rt || d.enc_prec < WD_FP32 || d.enc_prec > WD_HALF_F16))
     return hipErrorInvalidValue;
+  if (d.dot == DOT_ENC && (prec != WD_FP64 || !d.xpay || !d.dagger || d.basis != kBasisUK || !d.enc_rh ||
+                           !d.enc_xh || d.enc_prec < WD_FP32 || d.enc_prec > WD_HALF_F16))
+    return hipErrorInvalidValue;
   LaunchCfg c = tuned_dslash_config(g, prec, d, s);
   // A fused dot sums each workgroup's sites into one partial record; with one
   // sub-slab and 256-thread workgroups those site sets are fixed whatever the

@@ -1062,6 +1062,8 @@ __device__ __forceinline__ void hop_pair(Spinor<typename S::real> (&acc)[NR], co
 //   DOT_RES_ENC: r = y - (x + a * D in) re-encoded in format S2 into enc.rh
 //     (out is not written), enc.xh = 0, with enc.set_rt also enc.rt = enc(r);
 //     |r|^2, |enc(r)|^2, <enc.rt, enc(r)>
+//   DOT_ENC: x + a * D^dag in encoded in format S2 into enc.rh (out is not
+//     written), enc.xh = 0; |enc.rh|^2
 // Right-hand sides whose active flag in `sel` is 0 are skipped; with g.mapped,
 // `sel` instead lists the g.nrhs right-hand sides to process, packed into the
 // RHS slots of as few groups as they fill.  BASIS: spin basis of in, out, x
@@ -1119,10 +1121,35 @@ __device__ __forceinline__ void finish_rhs(const DslashGeom& g, Spinor<typename 
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc.v[s][c] = b.v[s][c] - acc.v[s][c];
     }
-    if constexpr (DOT != DOT_RES_ENC) {
+    if constexpr (DOT != DOT_RES_ENC && DOT != DOT_ENC) {
       if (g.out_nt) store_spinor<S, true>(out, r, cb, acc);
       else store_spinor<S>(out, r, cb, acc);
     }
+  }
+  if constexpr (DOT == DOT_ENC) {
+    using R2 = typename S2::real;
+    double d[1] = {0.0};
+    if (valid) {
+      Spinor<R2> e, z;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          e.v[s][c] = {static_cast<R2>(acc.v[s][c].re), static_cast<R2>(acc.v[s][c].im)};
+          z.v[s][c] = {R2(0), R2(0)};
+        }
+      store_spinor<S2>(enc.rh, r, cb, e);
+      store_spinor<S2>(enc.xh, r, cb, z);
+      load_spinor<S2>(enc.rh, r, cb, e);  // the norm of the stored (re-encoded) value
+      R2 n2 = 0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc_norm(n2, e.v[s][c]);
+      d[0] = n2;
+    }
+    const int nb = (g.slab ? 8 : 1) * g.site_blocks;
+    block_sum_store<1>(d, partials + ((int64_t)r * nb + pid) * kMaxDot);
   }
   if constexpr (DOT == DOT_RES_ENC) {
     using R2 = typename S2::real;
@@ -1160,7 +1187,7 @@ __device__ __forceinline__ void finish_rhs(const DslashGeom& g, Spinor<typename 
     const int nb = (g.slab ? 8 : 1) * g.site_blocks;
     block_sum_store<4>(d, partials + ((int64_t)r * nb + pid) * kMaxDot);
   }
-  if constexpr (DOT != DOT_NONE && DOT != DOT_RES_ENC) {
+  if constexpr (DOT != DOT_NONE && DOT != DOT_RES_ENC && DOT != DOT_ENC) {
     const int nb = (g.slab ? 8 : 1) * g.site_blocks;
     double* part = partials + ((int64_t)r * nb + pid) * kMaxDot;
     if constexpr (DOT == DOT_YO) {
@@ -1631,6 +1658,20 @@ static void launch_dot(int dot, unsigned grid, int block, size_t lds, hipStream_
               break;
             default:
               dslash_kernel<S, DAGGER, XPAY, DOT_RES_ENC, NR, RECON, LDS, BASIS, SF16><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+          }
+        }
+        break;
+      case DOT_ENC:
+        if constexpr (S::prec == WD_FP64 && XPAY && DAGGER && !LDS) {
+          switch (enc_prec) {
+            case WD_FP32:
+              dslash_kernel<S, DAGGER, XPAY, DOT_ENC, NR, RECON, LDS, BASIS, SF32><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+              break;
+            case WD_HALF_I16:
+              dslash_kernel<S, DAGGER, XPAY, DOT_ENC, NR, RECON, LDS, BASIS, SI16><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
+              break;
+            default:
+              dslash_kernel<S, DAGGER, XPAY, DOT_ENC, NR, RECON, LDS, BASIS, SF16><<<grid, block, lds, s>>>(g, links, fo, fi, fx, fy, a, p, sel, partials, enc);
           }
         }
         break;

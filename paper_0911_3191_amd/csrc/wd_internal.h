@@ -69,8 +69,10 @@ constexpr int kMaxDotHost = 4;  // doubles per partial record
 // solver's fields: enc_rh = enc(r), enc_xh = 0 (with enc_set_rt also the new
 // shadow residual enc_rt = enc(r), as defect correction restarts from it),
 // partials |r|^2, |enc(r)|^2, <enc_rt, enc(r)> (the last two on the stored
-// values).
-enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4, DOT_RES_ENC = 5 };
+// values).  DOT_ENC (FP64 adjoint, UKQCD basis): out = xpay + a D^dag in is
+// not stored in FP64 but encoded straight into enc_rh, enc_xh = 0, partial
+// |enc_rh|^2 on the stored value (CG's reliable update: r^ = enc(M_hat^dag r)).
+enum DotMode { DOT_NONE = 0, DOT_YO = 1, DOT_OX = 2, DOT_OO = 3, DOT_RES = 4, DOT_RES_ENC = 5, DOT_ENC = 6 };
 
 // Full argument set of one dslash launch.  out = D in, or, with xpay set,
 // out = *xpay + a * D in; with xpay and dot set, per-block FP64 partials of

@@ -267,10 +267,37 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map =
     WD_TRY(fin(h, fresh ? FIN_BICG_INIT : FIN_RHO, h->rumask, false));
   } else {
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
-    // normal-equation residual M_hat^dag r in FP64
-    WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask, n_map));
-    WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->rn, nullptr, h->rumask, h->partials, h->s));
-    WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask, false));
+    // normal-equation residual M_hat^dag r; r^ = it, x^ = 0.  With a 32- or
+    // 16-bit inner format the second FP64 dslash encodes it straight into r^
+    // and sums |r^|^2 of the stored values, so it is never written in FP64
+    // (h->rn is named as that launch's output, not written).
+    const bool fused = P != WD_FP64;
+    if (!fused) {
+      WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask, n_map));
+      WD_TRY(blas_reencode(g, P, h->rh, h->xh, h->rn, nullptr, h->rumask, h->partials, h->s));
+    } else {
+      WD_TRY(dslash_into(h, WD_FP64, h->to64, r64, 1, 1, nullptr, 0.0, DOT_NONE, nullptr, h->rumask, n_map));
+      DslashArgs d;
+      d.out = h->rn;
+      d.in = h->to64;
+      d.out_parity = 0;
+      d.dagger = 1;
+      d.xpay = &r64;
+      d.a = -h->kappa * h->kappa;
+      d.dot = DOT_ENC;
+      d.partials = h->partials;
+      d.active = h->rumask;
+      d.basis = kBasisUK;
+      d.enc_prec = P;
+      d.enc_rh = &h->rh;
+      d.enc_xh = &h->xh;
+      if (n_map > 0) {
+        d.rhs_map = h->rumap;
+        d.n_map = n_map;
+      }
+      WD_TRY(launch_dslash_ex(h->g, WD_FP64, d, h->s));
+    }
+    WD_TRY(fin(h, first ? FIN_CG_INIT : FIN_CG_RHO, h->rumask, fused));
     if (first) WD_TRY(blas_convert(g, P, h->p, P, h->rh, h->rumask, h->s));  // p = r^
   }
   return hipSuccess;
