@@ -39,8 +39,9 @@ static Layout layout(const Geom& g, int kind, wd_prec inner, int nrhs) {
   Layout L;
   L.hi_field = align256(spinor_field_bytes(g, WD_FP64, nrhs));
   L.lo_field = align256(spinor_field_bytes(g, inner, nrhs));
-  // high precision: b_hat, x, r (+ the normal-equation residual for CG) and an odd temporary
-  L.n_hi_even = (kind == WD_SOLVER_CG) ? 4 : 3;
+  // high precision: b_hat, x, r (+ the normal-equation residual for CG with an FP64 inner
+  // solver; with a 32- or 16-bit one it goes straight into r^) and an odd temporary
+  L.n_hi_even = (kind == WD_SOLVER_CG && inner == WD_FP64) ? 4 : 3;
   L.n_hi_odd = 1;
   // low precision: BiCGstab r^, r~, p, v, t, x^; CG r^, p, q, w, x^; plus an odd temporary
   L.n_lo_even = (kind == WD_SOLVER_CG) ? 5 : 6;
@@ -269,8 +270,8 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map =
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
     // normal-equation residual M_hat^dag r; r^ = it, x^ = 0.  With a 32- or
     // 16-bit inner format the second FP64 dslash encodes it straight into r^
-    // and sums |r^|^2 of the stored values, so it is never written in FP64
-    // (h->rn is named as that launch's output, not written).
+    // and sums |r^|^2 of the stored values: it is never stored in FP64, and
+    // that launch's output names no memory (its shape only sizes the launch).
     const bool fused = P != WD_FP64;
     if (!fused) {
       WD_TRY(mhat_into(h, WD_FP64, h->rn, r64, h->to64, 1, DOT_NONE, nullptr, h->rumask, n_map));
@@ -278,7 +279,7 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map =
     } else {
       WD_TRY(dslash_into(h, WD_FP64, h->to64, r64, 1, 1, nullptr, 0.0, DOT_NONE, nullptr, h->rumask, n_map));
       DslashArgs d;
-      d.out = h->rn;
+      d.out = Field{nullptr, h->geom.stride, h->nrhs};  // not written
       d.in = h->to64;
       d.out_parity = 0;
       d.dagger = 1;
@@ -461,7 +462,7 @@ wd_status wd_solver_begin(int32_t solver, const wd_gauge* g, double kappa, doubl
   h->bhat = take_hi();
   h->x = take_hi();
   h->r = take_hi();
-  h->rn = (solver == WD_SOLVER_CG) ? take_hi() : Field{nullptr, 0, 0};
+  h->rn = (solver == WD_SOLVER_CG && prm->inner == WD_FP64) ? take_hi() : Field{nullptr, 0, 0};
   h->to64 = take_hi();
   h->rh = take_lo();
   h->p = take_lo();
