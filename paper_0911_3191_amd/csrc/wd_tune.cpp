@@ -24,7 +24,10 @@
 // fastest: the best of two timings of five launches each, after a warm-up.
 // The search is greedy: nr, nsub, lds and rloop first, then the workgroup
 // size for the winner, then the occupancy cap for that; a subset launch
-// stops after the first stage with one sub-slab.  Launches made
+// stops after the first stage with one sub-slab.  Last, the (up to four)
+// shapes within 3% of the fastest are timed again over 20 launches each, in
+// two interleaved rounds, and the best of those longer timings wins: five
+// launches cannot separate shapes that close.  Launches made
 // while the stream is being captured into a graph, or whose output aliases
 // one of their inputs (xpay source, y, in), use the default shape and do not
 // tune.
@@ -34,7 +37,8 @@
 // link_nt lds rloop wgs" line per entry; flags = 1 for 8-real links + 2 for
 // temporal gauge + 4 for UKQCD-basis fields; form = 1 adjoint + 2 xpay +
 // 4 * dot mode + 32 mapped subset); WD_TUNE_VERBOSE=1 prints every timed
-// candidate to stderr; WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs
+// candidate to stderr (the final re-timings marked "re-timed");
+// WD_DSLASH_SHAPE="nr,gslow,nsub[,link_nt[,out_nt[,wgs
 // [,lds[,rloop[,block]]]]]]" forces a shape (the RHS-group-slowest order is
 // not searched: it never paid).
 #include <hip/hip_runtime.h>
@@ -45,6 +49,8 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
+#include <vector>
 
 #include "wd_internal.h"
 
@@ -128,10 +134,14 @@ bool verbose() {
   return e && e[0] == '1';
 }
 
-constexpr int kReps = 5;
+constexpr int kReps = 5;       // launches per timing in the search
+constexpr int kLongReps = 20;  // launches per timing of the finalists
+constexpr int kFinalists = 4;
+constexpr float kFinalistBand = 1.03f;
 
 // Milliseconds per launch of configuration c in the launch's own form, or -1.
-float time_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c, hipStream_t s) {
+float time_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const LaunchCfg& c, hipStream_t s,
+               int reps = kReps) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -140,12 +150,12 @@ float time_cfg(const wd_gauge* g, wd_prec prec, const DslashArgs& d, const Launc
   }
   launch_dslash_cfg(g, prec, d, c, s);  // warm-up
   (void)hipEventRecord(e0, s);
-  for (int i = 0; i < kReps; ++i) launch_dslash_cfg(g, prec, d, c, s);
+  for (int i = 0; i < reps; ++i) launch_dslash_cfg(g, prec, d, c, s);
   (void)hipEventRecord(e1, s);
   float ms = -1.0f;
   if (hipGetLastError() == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
       hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-    ms /= kReps;
+    ms /= reps;
   else
     ms = -1.0f;
   (void)hipEventDestroy(e0);
@@ -160,21 +170,54 @@ struct Search {
   hipStream_t s;
   LaunchCfg best;
   float best_ms = -1.0f;
+  std::vector<std::pair<LaunchCfg, float>> tried;  // every shape that launched, with its time
+
+  void report(const LaunchCfg& c, const char* tag, float ms) const {
+    if (verbose())
+      std::fprintf(stderr,
+                   "[wd tune] %dx%dx%dx%d prec %d nrhs %d form %d: nr %d nsub %d lds %d rloop %d block %d wgs %d"
+                   "%s -> %.1f us\n",
+                   g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, launch_rhs(d), form_of(d),
+                   c.nr, c.nsub, c.lds, c.rloop, c.block, c.wgs, tag, ms * 1e3f);
+  }
 
   // the better of two timings, so that a clock ramp-up does not decide
   void try_cfg(const LaunchCfg& c) {
     float ms = time_cfg(g, prec, d, c, s);
     const float ms2 = time_cfg(g, prec, d, c, s);
     if (ms2 > 0.0f && (ms < 0.0f || ms2 < ms)) ms = ms2;
-    if (verbose())
-      std::fprintf(stderr,
-                   "[wd tune] %dx%dx%dx%d prec %d nrhs %d form %d: nr %d nsub %d lds %d rloop %d block %d wgs %d"
-                   " -> %.1f us\n",
-                   g->geom.L[0], g->geom.L[1], g->geom.L[2], g->geom.L[3], (int)prec, launch_rhs(d), form_of(d),
-                   c.nr, c.nsub, c.lds, c.rloop, c.block, c.wgs, ms * 1e3f);
-    if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+    report(c, "", ms);
+    if (ms <= 0.0f) return;
+    tried.emplace_back(c, ms);
+    if (best_ms < 0.0f || ms < best_ms) {
       best_ms = ms;
       best = c;
+    }
+  }
+
+  // the shapes within the band of the fastest, timed again over longer runs
+  // in interleaved rounds; the best longer timing wins
+  void refine() {
+    std::vector<std::pair<LaunchCfg, float>> fin;
+    for (const auto& t : tried)
+      if (t.second <= best_ms * kFinalistBand) fin.push_back(t);
+    if (fin.size() < 2) return;
+    std::stable_sort(fin.begin(), fin.end(), [](const auto& a, const auto& b) { return a.second < b.second; });
+    if (fin.size() > (size_t)kFinalists) fin.resize(kFinalists);
+    std::vector<float> t(fin.size(), -1.0f);
+    for (int round = 0; round < 2; ++round)
+      for (size_t i = 0; i < fin.size(); ++i) {
+        const float ms = time_cfg(g, prec, d, fin[i].first, s, kLongReps);
+        if (ms > 0.0f && (t[i] < 0.0f || ms < t[i])) t[i] = ms;
+      }
+    int k = -1;
+    for (size_t i = 0; i < fin.size(); ++i) {
+      report(fin[i].first, " re-timed", t[i]);
+      if (t[i] > 0.0f && (k < 0 || t[i] < t[k])) k = (int)i;
+    }
+    if (k >= 0) {
+      best = fin[k].first;
+      best_ms = t[k];
     }
   }
 };
@@ -238,6 +281,8 @@ LaunchCfg run_tuner(const wd_gauge* g, wd_prec prec, const DslashArgs& d, hipStr
       S.try_cfg(c);
     }
   }
+  // 4. the finalists, timed again over longer runs
+  S.refine();
   return S.best;
 }
 

@@ -26,6 +26,10 @@ LINE = re.compile(r"\[wd tune\] (\S+) prec (\d+) nrhs (\d+) form (\d+): nr (\d+)
                   r"block (\d+) wgs (\d+) -> ")
 
 
+RETIMED = re.compile(r"\[wd tune\] (\S+) prec (\d+) nrhs (\d+) form (\d+): nr (\d+) nsub (\d+) lds (\d+) "
+                     r"rloop (\d+) block (\d+) wgs (\d+) re-timed -> ")
+
+
 def _cache_entries(path):
     """Cache file lines as (key, shape) dicts."""
     out = []
@@ -39,10 +43,10 @@ def _cache_entries(path):
     return out
 
 
-def _timed(err, dims):
+def _timed(err, dims, pattern=LINE):
     tag = "x".join(map(str, dims))
     return [dict(zip(("form", "nr", "nsub", "lds", "rloop", "block", "wgs"), map(int, m.groups()[3:])))
-            for m in map(LINE.match, err.splitlines()) if m and m.group(1) == tag]
+            for m in map(pattern.match, err.splitlines()) if m and m.group(1) == tag]
 
 
 def test_first_launch_tunes_once_and_records_its_choice(tmp_path, monkeypatch, capfd):
@@ -65,7 +69,9 @@ def test_first_launch_tunes_once_and_records_its_choice(tmp_path, monkeypatch, c
         return s.decode("f16", fout, nrhs, basis=UK)
 
     first = run()
-    timed = _timed(capfd.readouterr().err, dims)
+    err = capfd.readouterr().err
+    timed = _timed(err, dims)
+    retimed = _timed(err, dims, RETIMED)
     assert timed and all(t["form"] == 0 for t in timed)
     # stage 1: 1-3 RHS slots x 1 or 2 y-sub-slabs (Ly = 10) x LDS staging off / on, and
     # the RHS loop with 1 or 2 y-sub-slabs x LDS off / on, all at 256 threads, no cap
@@ -79,9 +85,15 @@ def test_first_launch_tunes_once_and_records_its_choice(tmp_path, monkeypatch, c
     stage3 = [t for t in timed if t["wgs"] != 0]
     assert {t["wgs"] for t in stage3} <= {2, 3, 4, 6} and 3 <= len(stage3) <= 4, timed
     assert len(timed) == len(stage1) + len(stage2) + len(stage3)
+    # stage 4: none, or two to four of the timed shapes timed again; the choice is one of them
+    assert len(retimed) == 0 or 2 <= len(retimed) <= 4, retimed
+    assert all(t in timed for t in retimed)
     entries = _cache_entries(cache)
     assert len(entries) == 1, entries
     e = entries[0]
+    if retimed:
+        keys = ("nr", "nsub", "lds", "rloop", "block", "wgs")
+        assert {k: e[k] for k in keys} in [{k: t[k] for k in keys} for t in retimed]
     assert (e["dims"], e["prec"], e["nrhs"], e["flags"], e["form"]) == (dims, 3, 3, 4, 0)  # UKQCD, D
     assert e["block"] in (128, 256, 512) and e["gslow"] == 0 and e["link_nt"] == 0 and e["wgs"] in (0, 2, 3, 4, 6)
     assert 1 <= e["nr"] <= 3 and e["nsub"] in (1, 2) and e["lds"] in (0, 1) and e["rloop"] in (0, 1)
@@ -176,6 +188,8 @@ def test_solver_tunes_every_form_before_capture(solver, tmp_path, monkeypatch, c
     fp64 = {(e["form"], e["nrhs"]) for e in entries if e["prec"] == 0}
     assert any(f & 32 for f, _ in fp64), fp64  # some reliable update covered a subset
     assert all(n < 4 for f, n in fp64 if f & 32)
+    if solver == "cg":  # the re-seed's adjoint xpay launch encodes M^dag r into r^ (dot mode 6)
+        assert any(f & 31 == 1 + 2 + 4 * 6 for f, _ in fp64), fp64
     for e in entries:  # fused dots keep one sub-slab and 256-thread workgroups
         if e["form"] & 2 and e["form"] >> 2 & 7:
             assert e["nsub"] == 1 and e["block"] == 256
