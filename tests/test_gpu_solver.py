@@ -88,7 +88,8 @@ def test_batch_of_five_with_staggered_updates_equals_each_rhs_alone(solver, rest
     """Five RHS of different structure reach their reliable updates at different
     iterations, so the updates run on packed subsets of the batch (BiCGstab
     re-encodes the residual inside the FP64 dslash; CG forms M_hat^dag r on the
-    same subset; defect correction also restarts there): every RHS must still
+    same subset and encodes it into r^ inside the second of those launches;
+    defect correction also restarts there): every RHS must still
     come out bit for bit as when solved alone, and solve the system."""
     dims, kappa = (8, 4, 8, 6), 0.124
     U = wdinputs.gauge_random(dims, 0.4, 13)
