@@ -249,22 +249,25 @@ __global__ void __launch_bounds__(kBlock) k_accum(int Vh, FieldView x, FieldView
   store_spinor<SF64>(x, rhs, i, X);
 }
 
-// f (FP64) <- f / |b| (down = 1) or f * |b| (down = 0), per RHS; |b| = 0 leaves f.
-__global__ void __launch_bounds__(kBlock) k_scale_bnorm(int Vh, FieldView f, const double* __restrict__ sc,
-                                                        int down) {
+// partials: |b|^2 of a canonical full-lattice FP64 array [nrhs][2 Vh][24]; thread i
+// sums lexicographic sites i and Vh + i, so a RHS has as many records as the
+// other BLAS-1 kernels.
+__global__ void __launch_bounds__(kBlock) k_canon_norm2(int Vh, const double* __restrict__ canon,
+                                                        double* __restrict__ partials) {
   const int rhs = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Vh) return;
-  const double bn = sc[rhs * SC_COUNT + SC_BNORM];
-  if (!(bn > 0.0) || !isfinite(bn)) return;
-  const double m = down ? 1.0 / bn : bn;
-  Spinor<double> a;
-  load_spinor<SF64>(f, rhs, i, a);
+  double d[1] = {0.0};
+  if (i < Vh) {
+    const double* a = canon + ((int64_t)rhs * 2 * Vh + i) * 24;
+    const double* b = a + (int64_t)Vh * 24;
+    double nn = 0.0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+    for (int n = 0; n < 24; ++n) nn += a[n] * a[n];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.v[s][c] = m * a.v[s][c];
-  store_spinor<SF64>(f, rhs, i, a);
+    for (int n = 0; n < 24; ++n) nn += b[n] * b[n];
+    d[0] = nn;
+  }
+  block_sum_store<1>(d, partials + ((int64_t)rhs * gridDim.x + blockIdx.x) * kMaxDot);
 }
 
 // rh <- enc(r64); xh <- 0; partials: |rh|^2, <rt, rh> (rt may be null).
@@ -334,9 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int stage, int nb, const do
   int* f = fl + rhs * FL_COUNT;
   const double stop = fa.tol * sqrt(s[SC_B2]);
   switch (stage) {
-    case FIN_B2_FIRST: s[SC_B2] = v[0]; break;
-    case FIN_B2_ADD: {  // |b|; the solve then runs on b / |b| (B2 becomes 1)
-      const double b2 = s[SC_B2] + v[0];
+    case FIN_B2: {  // |b|; the solve then runs on b / |b| (B2 becomes 1)
+      const double b2 = v[0];
       s[SC_BNORM] = sqrt(b2);
       s[SC_B2] = isfinite(b2) ? (b2 > 0.0 ? 1.0 : 0.0) : b2;
       break;
@@ -596,8 +598,8 @@ hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int*
   });
 }
 
-hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s) {
-  k_scale_bnorm<<<grid_of(g, f64.nrhs), kBlock, 0, s>>>(g.Vh, fv(f64), sc, down);
+hipError_t blas_canon_norm2(const Geom& g, const double* canon, int nrhs, double* partials, hipStream_t s) {
+  k_canon_norm2<<<grid_of(g, nrhs), kBlock, 0, s>>>(g.Vh, canon, partials);
   return hipGetLastError();
 }
 

@@ -118,13 +118,24 @@ __device__ __forceinline__ void change_basis(double (&v)[24], bool to_uk) {
   }
 }
 
+// Per-RHS factor of the solver's unit-source scaling: 1 / |b| (scale = 1) or
+// |b| (scale = 2) from the solver scalars sc; 1 without scaling or when |b|
+// is zero or not finite.
+__device__ __forceinline__ double bnorm_factor(const double* __restrict__ sc, int scale, int r) {
+  if (!scale) return 1.0;
+  const double bn = sc[r * SC_COUNT + SC_BNORM];
+  if (!(bn > 0.0) || !isfinite(bn)) return 1.0;
+  return scale == 1 ? 1.0 / bn : bn;
+}
+
 // full_parity < 0: canonical array is a parity array [nrhs][Vh][24];
 // full_parity = p: canonical array is a full lattice [nrhs][V][24] and the
 // field holds its parity-p sites.  The canonical array is in the
-// DeGrand-Rossi basis, the field in `basis`.
+// DeGrand-Rossi basis, the field in `basis`.  With scale, the values are
+// multiplied by bnorm_factor after the change of basis.
 template <class S>
 __global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __restrict__ canon,
-                                     int full_parity, int basis) {
+                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
   using R = typename S::real;
   const int cb = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -136,15 +147,22 @@ __global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __res
 #pragma unroll
   for (int n = 0; n < 24; ++n) v[n] = src[n];
   if (basis == kBasisUK) change_basis(v, true);
+  if (scale) {
+    const double k = bnorm_factor(sc, scale, r);
+#pragma unroll
+    for (int n = 0; n < 24; ++n) v[n] = k * v[n];
+  }
   Spinor<R> s;
 #pragma unroll
   for (int n = 0; n < 12; ++n) s.v[n / 3][n % 3] = {static_cast<R>(v[2 * n]), static_cast<R>(v[2 * n + 1])};
   store_spinor<S>(f, r, cb, s);
 }
 
+// With scale, the field's values are multiplied by bnorm_factor before the
+// change of basis.
 template <class S>
 __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict__ canon,
-                                     int full_parity, int basis) {
+                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
   using R = typename S::real;
   const int cb = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -160,6 +178,11 @@ __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict_
     v[2 * n] = static_cast<double>(s.v[n / 3][n % 3].re);
     v[2 * n + 1] = static_cast<double>(s.v[n / 3][n % 3].im);
   }
+  if (scale) {
+    const double k = bnorm_factor(sc, scale, r);
+#pragma unroll
+    for (int n = 0; n < 24; ++n) v[n] = k * v[n];
+  }
   if (basis == kBasisUK) change_basis(v, false);
 #pragma unroll
   for (int n = 0; n < 24; ++n) dst[n] = v[n];
@@ -167,44 +190,48 @@ __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict_
 
 template <class S>
 static hipError_t enc_typed(const Geom& g, Field f, const double* canon, int full_parity, int basis,
-                            hipStream_t s) {
+                            const double* sc, int scale, hipStream_t s) {
   const int block = 256;
   dim3 grid((g.Vh + block - 1) / block, f.nrhs);
   spinor_encode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
-                                                 canon, full_parity, basis);
+                                                 canon, full_parity, basis, sc, scale);
   return hipGetLastError();
 }
 
 template <class S>
 static hipError_t dec_typed(const Geom& g, double* canon, Field f, int full_parity, int basis,
-                            hipStream_t s) {
+                            const double* sc, int scale, hipStream_t s) {
   const int block = 256;
   dim3 grid((g.Vh + block - 1) / block, f.nrhs);
   spinor_decode_kernel<S><<<grid, block, 0, s>>>(site_map(g), FieldView{f.ptr, f.stride, f.nrhs},
-                                                 canon, full_parity, basis);
+                                                 canon, full_parity, basis, sc, scale);
   return hipGetLastError();
 }
 
 hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
-                                    int full_parity, hipStream_t s, int basis) {
+                                    int full_parity, hipStream_t s, int basis, const double* sc,
+                                    int scale) {
   if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
+  if (scale < 0 || scale > 2 || (scale && !sc)) return hipErrorInvalidValue;
   switch (p) {
-    case WD_FP64: return enc_typed<SF64>(g, f, canon, full_parity, basis, s);
-    case WD_FP32: return enc_typed<SF32>(g, f, canon, full_parity, basis, s);
-    case WD_HALF_I16: return enc_typed<SI16>(g, f, canon, full_parity, basis, s);
-    case WD_HALF_F16: return enc_typed<SF16>(g, f, canon, full_parity, basis, s);
+    case WD_FP64: return enc_typed<SF64>(g, f, canon, full_parity, basis, sc, scale, s);
+    case WD_FP32: return enc_typed<SF32>(g, f, canon, full_parity, basis, sc, scale, s);
+    case WD_HALF_I16: return enc_typed<SI16>(g, f, canon, full_parity, basis, sc, scale, s);
+    case WD_HALF_F16: return enc_typed<SF16>(g, f, canon, full_parity, basis, sc, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
-                                    int full_parity, hipStream_t s, int basis) {
+                                    int full_parity, hipStream_t s, int basis, const double* sc,
+                                    int scale) {
   if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
+  if (scale < 0 || scale > 2 || (scale && !sc)) return hipErrorInvalidValue;
   switch (p) {
-    case WD_FP64: return dec_typed<SF64>(g, canon, f, full_parity, basis, s);
-    case WD_FP32: return dec_typed<SF32>(g, canon, f, full_parity, basis, s);
-    case WD_HALF_I16: return dec_typed<SI16>(g, canon, f, full_parity, basis, s);
-    case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, basis, s);
+    case WD_FP64: return dec_typed<SF64>(g, canon, f, full_parity, basis, sc, scale, s);
+    case WD_FP32: return dec_typed<SF32>(g, canon, f, full_parity, basis, sc, scale, s);
+    case WD_HALF_I16: return dec_typed<SI16>(g, canon, f, full_parity, basis, sc, scale, s);
+    case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, basis, sc, scale, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -157,10 +157,14 @@ hipError_t launch_spinor_decode(const Geom& g, wd_prec p, double* canon, Field f
                                 hipStream_t s, int basis = kBasisDR);
 // full_parity = p: the canonical array is a full lattice [nrhs][V][24] and the
 // field holds (or provides) its parity-p sites; full_parity < 0: parity array.
+// scale = 1 / 2: the solver's unit-source scaling, values divided / multiplied
+// by the per-RHS |b| held in the solver scalars sc (see SC_BNORM).
 hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const double* canon,
-                                    int full_parity, hipStream_t s, int basis = kBasisDR);
+                                    int full_parity, hipStream_t s, int basis = kBasisDR,
+                                    const double* sc = nullptr, int scale = 0);
 hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
-                                    int full_parity, hipStream_t s, int basis = kBasisDR);
+                                    int full_parity, hipStream_t s, int basis = kBasisDR,
+                                    const double* sc = nullptr, int scale = 0);
 
 // ---- solver state on the device --------------------------------------------------
 // Per-RHS FP64 scalars (complex ones take two slots: re, im).
@@ -182,7 +186,7 @@ enum ScalarSlot {
 // that several iterations can run between two reads of the flags by the host.
 enum FlagSlot { FL_RU = 0, FL_BREAK = 1, FL_CONV = 2, FL_ITERS = 3, FL_COUNT = 4 };
 enum FinStage {
-  FIN_B2_FIRST, FIN_B2_ADD, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
+  FIN_B2, FIN_TRUE, FIN_RHO, FIN_BICG_INIT, FIN_BICG_ALPHA, FIN_BICG_OMEGA,
   FIN_BICG_ITER, FIN_CG_INIT, FIN_CG_ALPHA, FIN_CG_ITER, FIN_CG_RHO,
   FIN_TRUE_RHO,  // FIN_TRUE on v[0], then FIN_RHO on v[1..3] where iteration goes on
   FIN_TRUE_INIT  // FIN_TRUE on v[0], then FIN_BICG_INIT on v[1..3] where iteration goes on
@@ -204,7 +208,9 @@ hipError_t blas_zero(const Geom& g, wd_prec pr, Field f, const int* mask, hipStr
 hipError_t blas_norm2(const Geom& g, wd_prec pr, Field f, const int* mask, double* partials,
                       hipStream_t s);
 hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int* mask, hipStream_t s);
-hipError_t blas_scale_bnorm(const Geom& g, Field f64, const double* sc, int down, hipStream_t s);
+// partials: |b|^2 of a canonical full-lattice FP64 array [nrhs][2 Vh][24], the
+// record count per RHS of the BLAS-1 kernels.
+hipError_t blas_canon_norm2(const Geom& g, const double* canon, int nrhs, double* partials, hipStream_t s);
 hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
                          const int* mask, double* partials, hipStream_t s);
 // restart = 1 (defect correction): the update trigger compares |r^| with the

@@ -344,18 +344,14 @@ static hipError_t prepare(wd_solver* h) {
   const Geom& g = h->geom;
   const int n = h->nrhs;
   WD_TRY(solver_init_flags(n, h->fl, h->active, h->rumask, h->s));
-  // b_e -> r, b_o -> to64, rotated into the UKQCD basis every solver field
-  // uses (S is orthogonal: norms and inner products are those of the caller's
-  // basis); |b|^2 = |b_e|^2 + |b_o|^2
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK));
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK));
-  WD_TRY(blas_norm2(g, WD_FP64, h->r, nullptr, h->partials, h->s));
-  WD_TRY(fin(h, FIN_B2_FIRST, nullptr, false));
-  WD_TRY(blas_norm2(g, WD_FP64, h->to64, nullptr, h->partials, h->s));
-  WD_TRY(fin(h, FIN_B2_ADD, nullptr, false));
-  // solve for b / |b| (unit source per RHS); x is scaled back at reconstruction
-  WD_TRY(blas_scale_bnorm(g, h->r, h->sc, 1, h->s));
-  WD_TRY(blas_scale_bnorm(g, h->to64, h->sc, 1, h->s));
+  // |b| of the caller's source, then the solve runs on b / |b| (a unit source
+  // per RHS; x is scaled back when it is decoded): b_e / |b| -> r and
+  // b_o / |b| -> to64, rotated into the UKQCD basis every solver field uses
+  // (S is orthogonal: norms and inner products are those of the caller's basis)
+  WD_TRY(blas_canon_norm2(g, h->b_in, h->nrhs, h->partials, h->s));
+  WD_TRY(fin(h, FIN_B2, nullptr, false));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK, h->sc, 1));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
   // b_hat = b_e + kappa D_eo b_o
   WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_NONE, nullptr, nullptr));
   WD_TRY(blas_zero(g, WD_FP64, h->x, nullptr, h->s));
@@ -369,15 +365,15 @@ static hipError_t prepare(wd_solver* h) {
   return hipSuccess;
 }
 
-// x_o = b_o + kappa D_oe x_e, then both parities into the caller's x (back in
-// the DeGrand-Rossi basis).
+// x_o = b_o + kappa D_oe x_e for the unit source (b_o / |b| again into to64),
+// then both parities into the caller's x, times |b| and back in the
+// DeGrand-Rossi basis.
 static hipError_t reconstruct(wd_solver* h) {
   const Geom& g = h->geom;
-  WD_TRY(blas_scale_bnorm(g, h->x, h->sc, 0, h->s));  // undo the unit-source scaling
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK));
+  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
   WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, &h->to64, h->kappa, DOT_NONE, nullptr, nullptr));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s, kBasisUK));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s, kBasisUK));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s, kBasisUK, h->sc, 2));
+  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s, kBasisUK, h->sc, 2));
   return hipStreamSynchronize(h->s);
 }
 
