@@ -270,7 +270,8 @@ __global__ void __launch_bounds__(kBlock) k_canon_norm2(int Vh, const double* __
   block_sum_store<1>(d, partials + ((int64_t)rhs * gridDim.x + blockIdx.x) * kMaxDot);
 }
 
-// rh <- enc(r64); xh <- 0; partials: |rh|^2, <rt, rh> (rt may be null).
+// rh <- enc(r64); xh <- 0; partials: |rh|^2, <rt, rh> (has_rt = 0: no rt;
+// 1: rt read; 2: rt <- enc(r64) too, the shadow residual of a fresh start).
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_reencode(int Vh, FieldView rh, FieldView xh, FieldView r64,
                                                      FieldView rt, int has_rt,
@@ -293,12 +294,14 @@ __global__ void __launch_bounds__(kBlock) k_reencode(int Vh, FieldView rh, Field
         z.v[s][c] = {R(0), R(0)};
       }
     store_spinor<S>(rh, rhs, i, b);
+    if (has_rt == 2) store_spinor<S>(rt, rhs, i, b);
     store_spinor<S>(xh, rhs, i, z);
     // the dots see the stored (re-encoded) residual
     load_spinor<S>(rh, rhs, i, b);
     R nn = 0, re = 0, im = 0;
     Spinor<R> t;
-    if (has_rt) load_spinor<S>(rt, rhs, i, t);
+    if (has_rt == 1) load_spinor<S>(rt, rhs, i, t);
+    if (has_rt == 2) t = b;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -604,12 +607,13 @@ hipError_t blas_canon_norm2(const Geom& g, const double* canon, int nrhs, double
 }
 
 hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
-                         const int* mask, double* partials, hipStream_t s) {
+                         const int* mask, double* partials, hipStream_t s, bool set_rt) {
+  if (set_rt && !rt) return hipErrorInvalidValue;
   return by_prec(pr, [&](auto tag) {
     using S = decltype(tag);
     k_reencode<S><<<grid_of(g, rh.nrhs), kBlock, 0, s>>>(g.Vh, fv(rh), fv(xh), fv(r64),
                                                          rt ? fv(*rt) : FieldView{nullptr, 0, 0},
-                                                         rt ? 1 : 0, mask, partials);
+                                                         rt ? (set_rt ? 2 : 1) : 0, mask, partials);
   });
 }
 

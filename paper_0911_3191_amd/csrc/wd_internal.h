@@ -211,8 +211,10 @@ hipError_t blas_accum(const Geom& g, wd_prec pr, Field x64, Field xh, const int*
 // partials: |b|^2 of a canonical full-lattice FP64 array [nrhs][2 Vh][24], the
 // record count per RHS of the BLAS-1 kernels.
 hipError_t blas_canon_norm2(const Geom& g, const double* canon, int nrhs, double* partials, hipStream_t s);
+// rh <- enc(r64), xh <- 0; partials |rh|^2 and, with rt, <rt, rh>; set_rt
+// writes rt <- enc(r64) first (the same bits as rh).
 hipError_t blas_reencode(const Geom& g, wd_prec pr, Field rh, Field xh, Field r64, const Field* rt,
-                         const int* mask, double* partials, hipStream_t s);
+                         const int* mask, double* partials, hipStream_t s, bool set_rt = false);
 // restart = 1 (defect correction): the update trigger compares |r^| with the
 // residual the inner solve started from, and CG restarts with beta = 0.
 hipError_t solver_finalize(int stage, int nrhs, int nb, const double* partials, double* sc, int* fl,

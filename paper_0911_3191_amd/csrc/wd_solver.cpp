@@ -258,13 +258,12 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map =
   const Geom& g = h->geom;
   const wd_prec P = h->prm.inner;
   if (h->kind == WD_SOLVER_BICGSTAB) {
-    const bool fresh = first || h->prm.restart;
-    if (fresh) WD_TRY(blas_convert(g, P, h->rt, WD_FP64, r64, h->rumask, h->s));  // r~ = r
+    const bool fresh = first || h->prm.restart;  // then also r~ = r^
     if (!first && h->prm.restart) {
       WD_TRY(blas_zero(g, P, h->p, h->rumask, h->s));
       WD_TRY(blas_zero(g, P, h->v, h->rumask, h->s));
     }
-    WD_TRY(blas_reencode(g, P, h->rh, h->xh, r64, &h->rt, h->rumask, h->partials, h->s));
+    WD_TRY(blas_reencode(g, P, h->rh, h->xh, r64, &h->rt, h->rumask, h->partials, h->s, fresh));
     WD_TRY(fin(h, fresh ? FIN_BICG_INIT : FIN_RHO, h->rumask, false));
   } else {
     if (!first) WD_TRY(solver_cg_tighten(h->nrhs, h->sc, h->fl, h->rumask, h->prm.tol, h->s));
@@ -352,13 +351,12 @@ static hipError_t prepare(wd_solver* h) {
   WD_TRY(fin(h, FIN_B2, nullptr, false));
   WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK, h->sc, 1));
   WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
-  // b_hat = b_e + kappa D_eo b_o
-  WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_NONE, nullptr, nullptr));
+  // b_hat = b_e + kappa D_eo b_o, with |b_hat|^2 from the same launch.  x = 0,
+  // so r = b_hat - M_hat x is b_hat exactly: the convergence test and the
+  // first inner residual read b_hat (no further dslash needed)
+  WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_OO, nullptr, nullptr));
+  WD_TRY(fin(h, FIN_TRUE, nullptr, true));
   WD_TRY(blas_zero(g, WD_FP64, h->x, nullptr, h->s));
-  // x = 0, so r = b_hat - M_hat x is b_hat exactly: the convergence test and
-  // the first inner residual read b_hat (no dslash needed)
-  WD_TRY(blas_norm2(g, WD_FP64, h->bhat, nullptr, h->partials, h->s));
-  WD_TRY(fin(h, FIN_TRUE, nullptr, false));
   WD_TRY(blas_zero(g, h->prm.inner, h->p, nullptr, h->s));
   WD_TRY(blas_zero(g, h->prm.inner, h->v, nullptr, h->s));
   WD_TRY(reseed(h, true, h->bhat));
