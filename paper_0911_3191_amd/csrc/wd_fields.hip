@@ -128,21 +128,12 @@ __device__ __forceinline__ double bnorm_factor(const double* __restrict__ sc, in
   return scale == 1 ? 1.0 / bn : bn;
 }
 
-// full_parity < 0: canonical array is a parity array [nrhs][Vh][24];
-// full_parity = p: canonical array is a full lattice [nrhs][V][24] and the
-// field holds its parity-p sites.  The canonical array is in the
-// DeGrand-Rossi basis, the field in `basis`.  With scale, the values are
-// multiplied by bnorm_factor after the change of basis.
+// One site: 24 canonical reals (DeGrand-Rossi basis) into the field in
+// `basis`, times bnorm_factor after the change of basis when scale is set.
 template <class S>
-__global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __restrict__ canon,
-                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
+__device__ __forceinline__ void encode_site(FieldView f, int r, int cb, const double* __restrict__ src, int basis,
+                                            const double* __restrict__ sc, int scale) {
   using R = typename S::real;
-  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (cb >= m.Vh) return;
-  const int64_t V = 2 * (int64_t)m.Vh;
-  const double* src = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
-                                        : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
   double v[24];
 #pragma unroll
   for (int n = 0; n < 24; ++n) v[n] = src[n];
@@ -158,18 +149,12 @@ __global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __res
   store_spinor<S>(f, r, cb, s);
 }
 
-// With scale, the field's values are multiplied by bnorm_factor before the
-// change of basis.
+// One site back: the field's values, times bnorm_factor before the change of
+// basis when scale is set, into 24 canonical reals.
 template <class S>
-__global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict__ canon,
-                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
+__device__ __forceinline__ void decode_site(FieldView f, int r, int cb, double* __restrict__ dst, int basis,
+                                            const double* __restrict__ sc, int scale) {
   using R = typename S::real;
-  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (cb >= m.Vh) return;
-  const int64_t V = 2 * (int64_t)m.Vh;
-  double* dst = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
-                                  : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
   Spinor<R> s;
   load_spinor<S>(f, r, cb, s);
   double v[24];
@@ -186,6 +171,70 @@ __global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict_
   if (basis == kBasisUK) change_basis(v, false);
 #pragma unroll
   for (int n = 0; n < 24; ++n) dst[n] = v[n];
+}
+
+// full_parity < 0: canonical array is a parity array [nrhs][Vh][24];
+// full_parity = p: canonical array is a full lattice [nrhs][V][24] and the
+// field holds its parity-p sites.  The canonical array is in the
+// DeGrand-Rossi basis, the field in `basis`.
+template <class S>
+__global__ void spinor_encode_kernel(SiteMap m, FieldView f, const double* __restrict__ canon,
+                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (cb >= m.Vh) return;
+  const int64_t V = 2 * (int64_t)m.Vh;
+  const double* src = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
+                                        : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
+  encode_site<S>(f, r, cb, src, basis, sc, scale);
+}
+
+template <class S>
+__global__ void spinor_decode_kernel(SiteMap m, FieldView f, double* __restrict__ canon,
+                                     int full_parity, int basis, const double* __restrict__ sc, int scale) {
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (cb >= m.Vh) return;
+  const int64_t V = 2 * (int64_t)m.Vh;
+  double* dst = (full_parity < 0) ? canon + ((int64_t)r * m.Vh + cb) * 24
+                                  : canon + ((int64_t)r * V + lex_of(m, cb, full_parity)) * 24;
+  decode_site<S>(f, r, cb, dst, basis, sc, scale);
+}
+
+// Parity of lexicographic site L; its checkerboard index is L / 2 (Lx is even).
+__device__ __forceinline__ int parity_of(const SiteMap& m, int64_t L) {
+  const int64_t row = L / m.L[0];
+  const int x = (int)(L - row * m.L[0]);
+  const int y = (int)(row % m.L[1]);
+  const int64_t zt = row / m.L[1];
+  const int z = (int)(zt % m.L[2]);
+  const int t = (int)(zt / m.L[2]);
+  return (x + y + z + t) & 1;
+}
+
+// Both parities of a canonical full lattice [nrhs][V][24] in one pass: thread
+// L takes lexicographic site L, so the canonical array is read (or written)
+// in order, and fe / fo receive (or provide) the even / odd sites.
+template <class S>
+__global__ void spinor_encode_both_kernel(SiteMap m, FieldView fe, FieldView fo, const double* __restrict__ canon,
+                                          int basis, const double* __restrict__ sc, int scale) {
+  const int64_t V = 2 * (int64_t)m.Vh;
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (L >= V) return;
+  encode_site<S>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), canon + ((int64_t)r * V + L) * 24, basis, sc,
+                 scale);
+}
+
+template <class S>
+__global__ void spinor_decode_both_kernel(SiteMap m, FieldView fe, FieldView fo, double* __restrict__ canon,
+                                          int basis, const double* __restrict__ sc, int scale) {
+  const int64_t V = 2 * (int64_t)m.Vh;
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (L >= V) return;
+  decode_site<S>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), canon + ((int64_t)r * V + L) * 24, basis, sc,
+                 scale);
 }
 
 template <class S>
@@ -234,6 +283,30 @@ hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Fie
     case WD_HALF_F16: return dec_typed<SF16>(g, canon, f, full_parity, basis, sc, scale, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_spinor_encode_both(const Geom& g, Field fe, Field fo, const double* canon, hipStream_t s,
+                                     int basis, const double* sc, int scale) {
+  if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
+  if (scale < 0 || scale > 2 || (scale && !sc) || fe.nrhs != fo.nrhs) return hipErrorInvalidValue;
+  const int block = 256;
+  dim3 grid((unsigned)((2 * (int64_t)g.Vh + block - 1) / block), fe.nrhs);
+  spinor_encode_both_kernel<SF64><<<grid, block, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
+                                                         FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
+                                                         scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_decode_both(const Geom& g, double* canon, Field fe, Field fo, hipStream_t s,
+                                     int basis, const double* sc, int scale) {
+  if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
+  if (scale < 0 || scale > 2 || (scale && !sc) || fe.nrhs != fo.nrhs) return hipErrorInvalidValue;
+  const int block = 256;
+  dim3 grid((unsigned)((2 * (int64_t)g.Vh + block - 1) / block), fe.nrhs);
+  spinor_decode_both_kernel<SF64><<<grid, block, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
+                                                         FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
+                                                         scale);
+  return hipGetLastError();
 }
 
 hipError_t launch_spinor_encode(const Geom& g, wd_prec p, Field f, const double* canon,

@@ -165,6 +165,12 @@ hipError_t launch_spinor_encode_map(const Geom& g, wd_prec p, Field f, const dou
 hipError_t launch_spinor_decode_map(const Geom& g, wd_prec p, double* canon, Field f,
                                     int full_parity, hipStream_t s, int basis = kBasisDR,
                                     const double* sc = nullptr, int scale = 0);
+// Both parities of a full-lattice canonical array in one pass (FP64 fields):
+// even sites to / from fe, odd sites to / from fo; scale as above.
+hipError_t launch_spinor_encode_both(const Geom& g, Field fe, Field fo, const double* canon, hipStream_t s,
+                                     int basis, const double* sc = nullptr, int scale = 0);
+hipError_t launch_spinor_decode_both(const Geom& g, double* canon, Field fe, Field fo, hipStream_t s,
+                                     int basis, const double* sc = nullptr, int scale = 0);
 
 // ---- solver state on the device --------------------------------------------------
 // Per-RHS FP64 scalars (complex ones take two slots: re, im).

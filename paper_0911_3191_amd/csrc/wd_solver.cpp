@@ -349,8 +349,7 @@ static hipError_t prepare(wd_solver* h) {
   // (S is orthogonal: norms and inner products are those of the caller's basis)
   WD_TRY(blas_canon_norm2(g, h->b_in, h->nrhs, h->partials, h->s));
   WD_TRY(fin(h, FIN_B2, nullptr, false));
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->r, h->b_in, 0, h->s, kBasisUK, h->sc, 1));
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
+  WD_TRY(launch_spinor_encode_both(g, h->r, h->to64, h->b_in, h->s, kBasisUK, h->sc, 1));
   // b_hat = b_e + kappa D_eo b_o, with |b_hat|^2 from the same launch.  x = 0,
   // so r = b_hat - M_hat x is b_hat exactly: the convergence test and the
   // first inner residual read b_hat (no further dslash needed)
@@ -370,8 +369,7 @@ static hipError_t reconstruct(wd_solver* h) {
   const Geom& g = h->geom;
   WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
   WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, &h->to64, h->kappa, DOT_NONE, nullptr, nullptr));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->x, 0, h->s, kBasisUK, h->sc, 2));
-  WD_TRY(launch_spinor_decode_map(g, WD_FP64, h->x_out, h->to64, 1, h->s, kBasisUK, h->sc, 2));
+  WD_TRY(launch_spinor_decode_both(g, h->x_out, h->x, h->to64, h->s, kBasisUK, h->sc, 2));
   return hipStreamSynchronize(h->s);
 }
 
