@@ -303,6 +303,13 @@ static hipError_t reseed(wd_solver* h, bool first, const Field& r64, int n_map =
   return hipSuccess;
 }
 
+// Mixed-precision BiCGstab re-seeds r^ inside the FP64 dslash, so it never
+// writes the FP64 r after prepare, which therefore keeps b_o / |b| there for
+// the reconstruction.
+static bool fused_reseed(const wd_solver* h) {
+  return h->kind == WD_SOLVER_BICGSTAB && h->prm.inner != WD_FP64;
+}
+
 static hipError_t reliable_update(wd_solver* h) {
   // the RHS that flagged an update (the device's rumask), listed for the dslash
   int n = 0;
@@ -313,8 +320,7 @@ static hipError_t reliable_update(wd_solver* h) {
   else
     n = 0;  // every RHS (or, defensively, none listed): the mask alone
   WD_TRY(blas_accum(h->geom, h->prm.inner, h->x, h->xh, h->rumask, h->s));  // x += x^
-  if (h->kind == WD_SOLVER_BICGSTAB && h->prm.inner != WD_FP64)
-    return true_residual(h, h->rumask, n, true);  // r = b - M x; r^ = r, x^ = 0 in the same pass
+  if (fused_reseed(h)) return true_residual(h, h->rumask, n, true);  // r = b - M x; r^ = r, x^ = 0 in the same pass
   WD_TRY(true_residual(h, h->rumask, n));  // r = b - M x
   WD_TRY(reseed(h, false, h->r, n));       // r^ = r (CG: M_hat^dag r), x^ = 0
   return hipSuccess;
@@ -344,16 +350,18 @@ static hipError_t prepare(wd_solver* h) {
   const int n = h->nrhs;
   WD_TRY(solver_init_flags(n, h->fl, h->active, h->rumask, h->s));
   // |b| of the caller's source, then the solve runs on b / |b| (a unit source
-  // per RHS; x is scaled back when it is decoded): b_e / |b| -> r and
-  // b_o / |b| -> to64, rotated into the UKQCD basis every solver field uses
-  // (S is orthogonal: norms and inner products are those of the caller's basis)
+  // per RHS; x is scaled back when it is decoded)
   WD_TRY(blas_canon_norm2(g, h->b_in, h->nrhs, h->partials, h->s));
   WD_TRY(fin(h, FIN_B2, nullptr, false));
-  WD_TRY(launch_spinor_encode_both(g, h->r, h->to64, h->b_in, h->s, kBasisUK, h->sc, 1));
+  // b_e / |b| -> to64 and b_o / |b| -> r (held there for the reconstruction
+  // where the solve leaves r alone; fields hold either parity), rotated into
+  // the UKQCD basis every solver field uses (S is orthogonal: norms and inner
+  // products are those of the caller's basis)
+  WD_TRY(launch_spinor_encode_both(g, h->to64, h->r, h->b_in, h->s, kBasisUK, h->sc, 1));
   // b_hat = b_e + kappa D_eo b_o, with |b_hat|^2 from the same launch.  x = 0,
   // so r = b_hat - M_hat x is b_hat exactly: the convergence test and the
   // first inner residual read b_hat (no further dslash needed)
-  WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->to64, 0, 0, &h->r, h->kappa, DOT_OO, nullptr, nullptr));
+  WD_TRY(dslash_into(h, WD_FP64, h->bhat, h->r, 0, 0, &h->to64, h->kappa, DOT_OO, nullptr, nullptr));
   WD_TRY(fin(h, FIN_TRUE, nullptr, true));
   WD_TRY(blas_zero(g, WD_FP64, h->x, nullptr, h->s));
   WD_TRY(blas_zero(g, h->prm.inner, h->p, nullptr, h->s));
@@ -362,13 +370,17 @@ static hipError_t prepare(wd_solver* h) {
   return hipSuccess;
 }
 
-// x_o = b_o + kappa D_oe x_e for the unit source (b_o / |b| again into to64),
-// then both parities into the caller's x, times |b| and back in the
-// DeGrand-Rossi basis.
+// x_o = b_o + kappa D_oe x_e for the unit source (b_o / |b| from r where the
+// solve kept it, else encoded again into to64), then both parities into the
+// caller's x, times |b| and back in the DeGrand-Rossi basis.
 static hipError_t reconstruct(wd_solver* h) {
   const Geom& g = h->geom;
-  WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
-  WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, &h->to64, h->kappa, DOT_NONE, nullptr, nullptr));
+  const Field* bo = &h->r;
+  if (!fused_reseed(h)) {
+    WD_TRY(launch_spinor_encode_map(g, WD_FP64, h->to64, h->b_in, 1, h->s, kBasisUK, h->sc, 1));
+    bo = &h->to64;
+  }
+  WD_TRY(dslash_into(h, WD_FP64, h->to64, h->x, 1, 0, bo, h->kappa, DOT_NONE, nullptr, nullptr));
   WD_TRY(launch_spinor_decode_both(g, h->x_out, h->x, h->to64, h->s, kBasisUK, h->sc, 2));
   return hipStreamSynchronize(h->s);
 }
