@@ -249,24 +249,26 @@ __global__ void __launch_bounds__(kBlock) k_accum(int Vh, FieldView x, FieldView
   store_spinor<SF64>(x, rhs, i, X);
 }
 
-// partials: |b|^2 of a canonical full-lattice FP64 array [nrhs][2 Vh][24]; thread i
-// sums lexicographic sites i and Vh + i, so a RHS has as many records as the
-// other BLAS-1 kernels.
+// partials: |b|^2 of a canonical full-lattice FP64 array [nrhs][2 Vh][24] read
+// as 16-byte pairs in address order: block k sums pairs [24 kBlock k,
+// 24 kBlock (k + 1)) of its RHS (the reals of 2 kBlock sites), so a RHS has as
+// many records as the other BLAS-1 kernels.
 __global__ void __launch_bounds__(kBlock) k_canon_norm2(int Vh, const double* __restrict__ canon,
                                                         double* __restrict__ partials) {
   const int rhs = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double d[1] = {0.0};
-  if (i < Vh) {
-    const double* a = canon + ((int64_t)rhs * 2 * Vh + i) * 24;
-    const double* b = a + (int64_t)Vh * 24;
-    double nn = 0.0;
-#pragma unroll
-    for (int n = 0; n < 24; ++n) nn += a[n] * a[n];
-#pragma unroll
-    for (int n = 0; n < 24; ++n) nn += b[n] * b[n];
-    d[0] = nn;
+  const int64_t npair = 24 * (int64_t)Vh;  // 16-byte pairs per RHS
+  const double2* src = reinterpret_cast<const double2*>(canon) + (int64_t)rhs * npair;
+  const int64_t j0 = (int64_t)blockIdx.x * 24 * kBlock + threadIdx.x;
+  double nn = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < 24; ++k) {
+    const int64_t j = j0 + (int64_t)k * kBlock;
+    if (j < npair) {
+      const double2 v = src[j];
+      nn += v.x * v.x + v.y * v.y;
+    }
   }
+  double d[1] = {nn};
   block_sum_store<1>(d, partials + ((int64_t)rhs * gridDim.x + blockIdx.x) * kMaxDot);
 }
 

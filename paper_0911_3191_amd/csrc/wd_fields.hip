@@ -212,29 +212,49 @@ __device__ __forceinline__ int parity_of(const SiteMap& m, int64_t L) {
   return (x + y + z + t) & 1;
 }
 
-// Both parities of a canonical full lattice [nrhs][V][24] in one pass: thread
-// L takes lexicographic site L, so the canonical array is read (or written)
-// in order, and fe / fo receive (or provide) the even / odd sites.
-template <class S>
-__global__ void spinor_encode_both_kernel(SiteMap m, FieldView fe, FieldView fo, const double* __restrict__ canon,
-                                          int basis, const double* __restrict__ sc, int scale) {
+// Both parities of a canonical full lattice [nrhs][V][24] (FP64 fields) in one
+// pass: a workgroup takes kBothSites consecutive lexicographic sites, whose
+// canonical records form one contiguous block that is read (or written)
+// with 16-byte accesses in address order and passed through LDS; thread k
+// works on site L0 + k, whose even / odd sites come from (go to) fe / fo.
+constexpr int kBothSites = 256;
+
+__global__ void __launch_bounds__(kBothSites) spinor_encode_both_kernel(SiteMap m, FieldView fe, FieldView fo,
+                                                                         const double* __restrict__ canon,
+                                                                         int basis, const double* __restrict__ sc,
+                                                                         int scale) {
+  __shared__ double2 tile[kBothSites * 12];
   const int64_t V = 2 * (int64_t)m.Vh;
-  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t L0 = (int64_t)blockIdx.x * kBothSites;
   const int r = blockIdx.y;
-  if (L >= V) return;
-  encode_site<S>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), canon + ((int64_t)r * V + L) * 24, basis, sc,
-                 scale);
+  const int n = (int)min((int64_t)kBothSites, V - L0);  // sites in this block
+  const double2* src = reinterpret_cast<const double2*>(canon + ((int64_t)r * V + L0) * 24);
+  for (int j = threadIdx.x; j < n * 12; j += kBothSites) tile[j] = src[j];
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k >= n) return;
+  const int64_t L = L0 + k;
+  encode_site<SF64>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), reinterpret_cast<const double*>(tile + 12 * k),
+                    basis, sc, scale);
 }
 
-template <class S>
-__global__ void spinor_decode_both_kernel(SiteMap m, FieldView fe, FieldView fo, double* __restrict__ canon,
-                                          int basis, const double* __restrict__ sc, int scale) {
+__global__ void __launch_bounds__(kBothSites) spinor_decode_both_kernel(SiteMap m, FieldView fe, FieldView fo,
+                                                                         double* __restrict__ canon, int basis,
+                                                                         const double* __restrict__ sc, int scale) {
+  __shared__ double2 tile[kBothSites * 12];
   const int64_t V = 2 * (int64_t)m.Vh;
-  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t L0 = (int64_t)blockIdx.x * kBothSites;
   const int r = blockIdx.y;
-  if (L >= V) return;
-  decode_site<S>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), canon + ((int64_t)r * V + L) * 24, basis, sc,
-                 scale);
+  const int n = (int)min((int64_t)kBothSites, V - L0);
+  const int k = threadIdx.x;
+  if (k < n) {
+    const int64_t L = L0 + k;
+    decode_site<SF64>(parity_of(m, L) ? fo : fe, r, (int)(L >> 1), reinterpret_cast<double*>(tile + 12 * k), basis,
+                      sc, scale);
+  }
+  __syncthreads();
+  double2* dst = reinterpret_cast<double2*>(canon + ((int64_t)r * V + L0) * 24);
+  for (int j = threadIdx.x; j < n * 12; j += kBothSites) dst[j] = tile[j];
 }
 
 template <class S>
@@ -289,11 +309,10 @@ hipError_t launch_spinor_encode_both(const Geom& g, Field fe, Field fo, const do
                                      int basis, const double* sc, int scale) {
   if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
   if (scale < 0 || scale > 2 || (scale && !sc) || fe.nrhs != fo.nrhs) return hipErrorInvalidValue;
-  const int block = 256;
-  dim3 grid((unsigned)((2 * (int64_t)g.Vh + block - 1) / block), fe.nrhs);
-  spinor_encode_both_kernel<SF64><<<grid, block, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
-                                                         FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
-                                                         scale);
+  dim3 grid((unsigned)((2 * (int64_t)g.Vh + kBothSites - 1) / kBothSites), fe.nrhs);
+  spinor_encode_both_kernel<<<grid, kBothSites, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
+                                                        FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
+                                                        scale);
   return hipGetLastError();
 }
 
@@ -301,11 +320,10 @@ hipError_t launch_spinor_decode_both(const Geom& g, double* canon, Field fe, Fie
                                      int basis, const double* sc, int scale) {
   if (basis != kBasisDR && basis != kBasisUK) return hipErrorInvalidValue;
   if (scale < 0 || scale > 2 || (scale && !sc) || fe.nrhs != fo.nrhs) return hipErrorInvalidValue;
-  const int block = 256;
-  dim3 grid((unsigned)((2 * (int64_t)g.Vh + block - 1) / block), fe.nrhs);
-  spinor_decode_both_kernel<SF64><<<grid, block, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
-                                                         FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
-                                                         scale);
+  dim3 grid((unsigned)((2 * (int64_t)g.Vh + kBothSites - 1) / kBothSites), fe.nrhs);
+  spinor_decode_both_kernel<<<grid, kBothSites, 0, s>>>(site_map(g), FieldView{fe.ptr, fe.stride, fe.nrhs},
+                                                        FieldView{fo.ptr, fo.stride, fo.nrhs}, canon, basis, sc,
+                                                        scale);
   return hipGetLastError();
 }
 
