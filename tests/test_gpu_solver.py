@@ -194,6 +194,26 @@ def test_maxiter_returns_not_converged_with_best_iterate():
     assert np.all(np.isfinite(x))
 
 
+@pytest.mark.parametrize("solver,inner", [("bicgstab", "f16"), ("cg", "i16")])
+@pytest.mark.parametrize("e", [133, -133])
+def test_solution_scales_with_the_source_bit_for_bit(solver, inner, e):
+    """The solve runs on b / |b| and scales x back, so a source times 2^e (here
+    beyond the binary32 range the 16-bit formats keep their norms in) gives
+    exactly 2^e times the solution of the unscaled source: powers of two scale
+    every rounding step of the path exactly."""
+    dims, kappa = (8, 4, 8, 6), 0.124
+    U = wdinputs.gauge_random(dims, 0.4, 13)
+    s = Setup(dims, U)
+    b = wdinputs.spinor_gaussian(dims, 31)
+    c = 2.0 ** e
+    st0, x0, info0 = run(s, solver, b, kappa, tol=1e-12, inner=inner, delta=0.1)
+    st1, x1, info1 = run(s, solver, b * c, kappa, tol=1e-12, inner=inner, delta=0.1)
+    assert st0 == wd.WD_OK and st1 == wd.WD_OK
+    assert np.array_equal(x1, x0 * c)
+    assert info1["iters"] == info0["iters"] and info1["true_rel_resid"] == info0["true_rel_resid"]
+    assert oracle.true_relres(dims, U, kappa, b * c, x1) <= 1e-12
+
+
 def test_zero_source_gives_zero_solution():
     dims, kappa = (4, 4, 4, 4), 0.12
     U = wdinputs.gauge_random(dims, 0.3, 15)
